@@ -1,0 +1,189 @@
+/*
+ * sdnn.h -- C ABI of the MI355X (gfx950) layered sparse-DNN library.
+ *
+ * The library runs the computation that dominates the paper's large sparse
+ * neural-network workload (section "Large Sparse Neural Network Inference"):
+ * inference of a stack of L sparse layers over a batch of input rows,
+ *
+ *     Y_{l+1} = min(c, max(0, Y_l W_l + b_l)),      l = 0 .. L-1,   c = 32,
+ *
+ * where every output neuron j of W_l has exactly k = 32 input neurons.  The
+ * paper checks the result against "truth categories"; here the equivalent
+ * output is the ascending list of rows whose final activations are nonzero.
+ * The paper issues the GPU work of that workload as task graphs (section
+ * "Heterogeneous Tasking", the cudaFlow; section "Scheduling GPU Tasks", one
+ * graph per cudaFlow submitted in a single call); the forward pass here can run
+ * as one hipGraph of per-layer kernels, as one
+ * persistent cooperative kernel, or as eager launches (sdnn_set_exec).
+ * A backward pass (gradients of W values on the fixed pattern, of b and of Y_0)
+ * with layer checkpointing is provided for training.
+ *
+ * Conventions for every entry point:
+ *  - All pointers named "dev" are HIP device pointers; "host" pointers are host
+ *    memory.  The caller allocates every buffer (the library allocates nothing
+ *    on the device except hipGraph objects); the library never frees them.
+ *  - Row-major fp32 activations: row r of a [rows][N] matrix starts at r*N.
+ *  - Layer tensors are stacked: idx/w are [L][N][k] (neuron-major: slot s of
+ *    neuron j of layer l at (l*N + j)*k + s), bias is [L][N].  Each neuron's
+ *    k input ids must be distinct and ascending, in [0, N).
+ *  - "stream" is a hipStream_t passed as void* (NULL = the default stream).
+ *    Compute entry points only enqueue work and never synchronize the host;
+ *    argument errors are reported synchronously and launch nothing.
+ *  - Every function returns an sdnn_status; sdnn_last_error() gives a
+ *    thread-local message for the last failure on the calling thread.
+ *  - Concurrent calls on one sdnn_net must be serialized by the caller (they
+ *    share the workspace).
+ */
+#ifndef SDNN_H
+#define SDNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sdnn_net_s *sdnn_net;
+
+typedef enum {
+    SDNN_OK = 0,
+    SDNN_EINVAL = -1,        /* bad argument; nothing was launched */
+    SDNN_ENOMEM = -2,        /* workspace / checkpoint buffer too small */
+    SDNN_EHIP = -3,          /* a HIP runtime call failed */
+    SDNN_EUNSUPPORTED = -4,  /* valid request the library does not implement (e.g. k != 32) */
+    SDNN_EDEVICE = -5        /* a kernel reported an error (barrier time-out, bad batch offsets) */
+} sdnn_status;
+
+/* sdnn_desc.flags */
+#define SDNN_TRAINABLE     0x1u  /* build the transposed pattern; enables sdnn_backward */
+#define SDNN_NO_COMPACTION 0x2u  /* process every row in every layer (results are identical) */
+#define SDNN_DEBUG_CHECKS  0x4u  /* validate idx/w/bias on the device at create time (synchronizes) */
+#define SDNN_AUTOTUNE      0x8u  /* time the kernel variants at create time and keep the fastest */
+
+/* sdnn_set_exec modes */
+#define SDNN_EXEC_AUTO         0 /* GRAPH for one batch, GRAPH_MERGED for several */
+#define SDNN_EXEC_EAGER        1 /* one kernel launch per layer, batches one after another */
+#define SDNN_EXEC_GRAPH        2 /* one hipGraph; batches one after another ("plain" form) */
+#define SDNN_EXEC_PERSISTENT   3 /* all layers of all batches in one cooperative kernel ("batched") */
+#define SDNN_EXEC_GRAPH_MERGED 4 /* one hipGraph whose layer nodes serve all batches ("batched") */
+
+typedef struct {
+    int32_t n_neurons;   /* N >= 1 (N <= 2^20) */
+    int32_t n_layers;    /* L >= 1 */
+    int32_t k;           /* inputs per neuron; must be 32 (else SDNN_EUNSUPPORTED) */
+    float clamp;         /* c > 0 (32 for the challenge networks) */
+    int32_t ckpt_every;  /* backward checkpoint stride S (>= 1) when SDNN_TRAINABLE, else 0 */
+    uint32_t flags;      /* SDNN_* flags above */
+    int64_t max_rows;    /* largest `rows` any later call will pass (workspace capacity) */
+} sdnn_desc;
+
+/* The tile plan of the forward layer kernel (chosen by heuristic or autotuner). */
+typedef struct {
+    int32_t rows_per_tile;   /* T: activation rows staged per workgroup tile */
+    int32_t threads;         /* workgroup size */
+    int32_t grid;            /* workgroups per layer launch (grid-stride over tiles) */
+    int32_t variant;         /* 0 = LDS-staged rows, 1 = direct gather (rows too wide for LDS) */
+    float tuned_us;          /* measured time per full-live layer of the tuning shape (0 if untuned) */
+} sdnn_plan;
+
+/* Bytes of device workspace sdnn_create needs for this descriptor. */
+sdnn_status sdnn_workspace_size(const sdnn_desc *desc, size_t *bytes);
+
+/* Bytes of the checkpoint buffer a forward over `rows` rows must be given so that
+ * sdnn_backward can run from it: (ceil(L / S) - 1) * rows * N * 4. */
+sdnn_status sdnn_ckpt_size(const sdnn_desc *desc, int64_t rows, size_t *bytes);
+
+/*
+ * Create a network over caller-owned parameters.
+ *   idx  dev int32 [L][N][k], w dev fp32 [L][N][k], bias dev fp32 [L][N].
+ *   These are BORROWED: they must stay alive and keep their pattern until
+ *   sdnn_destroy.  w and bias may be updated in place between calls (training).
+ *   workspace: dev buffer of at least sdnn_workspace_size bytes, 256-B aligned,
+ *   owned by the caller, used exclusively by this net until sdnn_destroy.
+ * If any bias is > 0, an all-zero row no longer stays all-zero, so compaction and
+ * early exit are switched off for the whole net (results are unchanged).
+ * Synchronizes `stream` (create is not a timed path).
+ */
+sdnn_status sdnn_create(const sdnn_desc *desc, const int32_t *idx, const float *w, const float *bias,
+                        void *workspace, size_t ws_bytes, void *stream, sdnn_net *out);
+
+/* Choose how sdnn_forward runs the layer chain (SDNN_EXEC_*). */
+sdnn_status sdnn_set_exec(sdnn_net net, int32_t mode);
+
+/* Read the current tile plan. */
+sdnn_status sdnn_get_plan(sdnn_net net, sdnn_plan *plan);
+
+/* Time every kernel variant that fits on a full-live layer of `rows` rows (rows <=
+ * max_rows; uses the workspace as scratch) and keep the fastest.  Synchronizes. */
+sdnn_status sdnn_tune(sdnn_net net, int64_t rows, void *stream);
+
+/*
+ * Forward pass over `rows` input rows.
+ *   y0        dev fp32 [rows][N]   input activations (not modified)
+ *   batch_off host int64 [n_batches+1] ascending offsets, 0 .. rows, or NULL
+ *             (one batch).  Batches are consecutive row ranges; rows are
+ *             independent, so results never depend on the split.  With
+ *             SDNN_EXEC_GRAPH / EAGER batches run one after another ("plain");
+ *             with SDNN_EXEC_PERSISTENT all batches run in one launch.
+ *   y_out     dev fp32 [rows][N]   final activations; rows that became all-zero
+ *             are exactly zero.  Must not overlap y0.  Also used as one of the
+ *             two ping-pong activation buffers.
+ *   nz_rows   dev int32 [rows]     ascending ids of rows with a nonzero final
+ *             activation (the "categories" output); entries past n_nz undefined.
+ *   n_nz      dev int32 [1]        number of such rows.
+ *   ckpt      dev fp32, sdnn_ckpt_size bytes, or NULL: receives Y_S, Y_2S, ...
+ *             (rows alive at that layer) for sdnn_backward.
+ *   layer_rows dev int32 [L+1] or NULL: layer_rows[l] = rows processed by layer l
+ *             (layer 0 processes every row), layer_rows[L] = n_nz.
+ */
+sdnn_status sdnn_forward(sdnn_net net, const float *y0, int64_t rows, const int64_t *batch_off, int32_t n_batches,
+                         float *y_out, int32_t *nz_rows, int32_t *n_nz, float *ckpt, int32_t *layer_rows,
+                         void *stream);
+
+/*
+ * One layer over all `rows` rows, no compaction: y_out = min(c, max(0, y_in W_l + b_l)).
+ * Used to check the forward layer by layer.  y_in/y_out dev fp32 [rows][N], must not overlap.
+ */
+sdnn_status sdnn_layer(sdnn_net net, int32_t layer, const float *y_in, int64_t rows, float *y_out, void *stream);
+
+/*
+ * Backward pass of the last sdnn_forward over the same y0 / rows / ckpt (needs
+ * SDNN_TRAINABLE).  Only rows listed in nz_rows can carry a gradient (every other
+ * row is all-zero after some layer, where the mask 0 < y < c stops it), so the
+ * pass runs on those rows, recomputing each checkpoint segment of S layers.
+ *   nz_rows, n_nz  dev, as written by that forward
+ *   dy_out    dev fp32 [rows][N]   dL/dY_L
+ *   dw        dev fp32 [L][N][k]   dL/dw  (overwritten)
+ *   dbias     dev fp32 [L][N]      dL/db  (overwritten)
+ *   dy0       dev fp32 [rows][N] or NULL: dL/dY_0 (overwritten)
+ * Deterministic: no floating-point atomics; every sum has a fixed order.
+ */
+sdnn_status sdnn_backward(sdnn_net net, const float *y0, int64_t rows, const float *ckpt, const int32_t *nz_rows,
+                          const int32_t *n_nz, const float *dy_out, float *dw, float *dbias, float *dy0,
+                          void *stream);
+
+/*
+ * Mean-squared-error loss of y against t (n elements) and its gradient:
+ *   dy (dev fp32 [n], may be NULL) = 2 (y - t) / n
+ *   loss (dev fp32 [257], may be NULL): loss[0] = sum (y - t)^2 / n; loss[1..256]
+ *   are scratch for per-block partial sums.  The loss is reduced in a fixed order.
+ */
+sdnn_status sdnn_mse(const float *y, const float *t, int64_t n, float *dy, float *loss, void *stream);
+
+/* Synchronize `stream` and report whether a kernel of this net raised its error word. */
+sdnn_status sdnn_check_device(sdnn_net net, void *stream);
+
+/* Release the net (NULL-safe).  Does not free caller buffers. */
+void sdnn_destroy(sdnn_net net);
+
+/* Thread-local message of the last failure. */
+const char *sdnn_last_error(void);
+
+/* Library version string. */
+const char *sdnn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SDNN_H */

@@ -67,6 +67,9 @@ def lib() -> ctypes.CDLL:
         L.orc_layer_backward.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_double,
                                          P, P, P, P, P, P, ctypes.c_int]
         L.orc_layer_backward.restype = None
+        L.orc_layer_bound.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_double, P, P,
+                                      P, ctypes.c_int]
+        L.orc_layer_bound.restype = None
         L.orc_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -142,6 +145,22 @@ def layer_backward(idx, w, clamp: float, y_in, y_out, dy_out, want_dy_in: bool =
     return dw, db, dy_in
 
 
+def layer_bound(idx, w, b, y_in, e_in=None, threads: int = 0) -> np.ndarray:
+    """Forward error bound of any fp32 evaluation of one layer (see sdnn_oracle.c)."""
+    idx, w, b = _check_layer(idx, w, b)
+    N, K = idx.shape
+    y_in = np.ascontiguousarray(y_in, np.float64)
+    R = y_in.shape[0]
+    if e_in is not None:
+        e_in = np.ascontiguousarray(e_in, np.float64)
+        if e_in.shape != y_in.shape:
+            raise ValueError("e_in must match y_in")
+    e_out = np.empty((R, N), np.float64)
+    if R:
+        lib().orc_layer_bound(R, N, K, _p(idx), _p(w), _p(b), gamma(33), _p(y_in), _p(e_in), _p(e_out), int(threads))
+    return e_out
+
+
 def ambiguous(z: np.ndarray, s: np.ndarray, clamp: float) -> np.ndarray:
     """Boolean mask of tie-ambiguous outputs (see the module docstring)."""
     tol = gamma(33) * s
@@ -155,6 +174,7 @@ class ForwardResult:
     alive_after: List[int]                # |rows alive after layer l|, l = 0..L-1
     ambiguous: List[int] = field(default_factory=list)   # tie-ambiguous outputs per layer (if asked)
     ys: Optional[List[np.ndarray]] = None  # Y_0..Y_L, each [B][N] double (if asked)
+    bound: Optional[np.ndarray] = None    # [B][N] forward error bound of any fp32 evaluation (if asked)
 
     @property
     def nz_rows(self) -> np.ndarray:
@@ -162,15 +182,19 @@ class ForwardResult:
 
 
 def forward(layers: Iterable[Tuple[np.ndarray, np.ndarray, np.ndarray]], y0: np.ndarray, clamp: float = 32.0,
-            compact: bool = True, keep: bool = False, ties: bool = False, threads: int = 0) -> ForwardResult:
+            compact: bool = True, keep: bool = False, ties: bool = False, bound: bool = False,
+            threads: int = 0) -> ForwardResult:
     """Run the layer chain over all rows of ``y0`` ([B][N]).
 
     ``layers`` yields (idx [N][K], w [N][K], b [N]) in layer order (a generator is fine,
     so a large net can be drawn one layer at a time).  With ``compact`` rows that are
-    all zero are skipped while every bias met so far is <= 0.
+    all zero are skipped while every bias met so far is <= 0.  With ``bound`` the
+    forward error bound of any fp32 evaluation of the chain is propagated too
+    (over every row: a row an fp32 evaluation keeps alive may be dead here).
     """
     y = np.array(y0, dtype=np.float64, copy=True)
     B = y.shape[0]
+    err = np.zeros_like(y) if bound else None
     act = np.ones(B, bool) if not compact else (y != 0).any(axis=1)
     alive_after: List[int] = []
     amb: List[int] = []
@@ -180,6 +204,8 @@ def forward(layers: Iterable[Tuple[np.ndarray, np.ndarray, np.ndarray]], y0: np.
         if compact and b.size and float(b.max()) > 0.0:
             act = np.ones(B, bool)        # a positive bias revives all-zero rows: treat every row
         rows = np.flatnonzero(act)
+        if bound:
+            err = layer_bound(idx, w, b, y, err, threads=threads)
         y_rows, a_rows, z, s = layer_forward(idx, w, b, clamp, y[rows], want_zs=ties, threads=threads)
         if ties:
             amb.append(int(ambiguous(z, s, clamp).sum()))
@@ -193,7 +219,7 @@ def forward(layers: Iterable[Tuple[np.ndarray, np.ndarray, np.ndarray]], y0: np.
         if keep:
             ys.append(y.copy())
     alive = (y != 0).any(axis=1)
-    return ForwardResult(y=y, alive=alive, alive_after=alive_after, ambiguous=amb, ys=ys)
+    return ForwardResult(y=y, alive=alive, alive_after=alive_after, ambiguous=amb, ys=ys, bound=err)
 
 
 def backward(layers: Sequence[Tuple[np.ndarray, np.ndarray, np.ndarray]], ys: Sequence[np.ndarray],
@@ -229,5 +255,5 @@ def teacher_outputs(layers_teacher, y0, clamp: float = 32.0, threads: int = 0) -
     return forward(layers_teacher, y0, clamp, compact=True, threads=threads).y.astype(np.float32)
 
 
-__all__ = ["build", "lib", "gamma", "layer_forward", "layer_backward", "ambiguous", "forward", "backward",
+__all__ = ["build", "lib", "gamma", "layer_forward", "layer_backward", "layer_bound", "ambiguous", "forward", "backward",
            "ForwardResult", "mse", "teacher_outputs", "max_threads", "U_FP32"]

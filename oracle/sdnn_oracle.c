@@ -28,6 +28,16 @@
  *     dW[j][k]         = sum_r G[r][j] * y_l[r][idx[j][k]]
  *     dY_l[r][i]       = sum_{(j,k) : idx[j][k] = i} G[r][j] * w[j][k]
  *
+ * Forward error bound.  Any fp32 evaluation of one layer (products and sums in
+ * any order, with or without fused multiply-adds) from inputs that differ from
+ * the exact ones by at most e_in satisfies, to first order,
+ *     |y_fp32 - y| <= (1 + g) sum_k |w| e_in[idx] + g (sum_k |w y| + |b|),
+ * g = gamma_33 = 33u / (1 - 33u) (32 products and one bias add, u = 2^-24):
+ * the sum of 33 rounded terms has error at most gamma_33 times the sum of their
+ * magnitudes, the input errors pass through with the weights' magnitudes, and
+ * min(c, max(0, .)) is 1-Lipschitz so it never enlarges an error.  Applying this
+ * layer by layer gives a bound for the whole chain.
+ *
  * Rows are independent: every function below treats the R rows it is given
  * and knows nothing of compaction, batches or checkpoints; the Python driver
  * next to this file strings layers together.
@@ -149,6 +159,36 @@ void orc_layer_backward(int64_t R, int32_t N, int32_t K,
             const int32_t *ij = idx + (int64_t)jj * K;
             const float *wj = w + (int64_t)jj * K;
             for (int32_t k = 0; k < K; ++k) di[ij[k]] += g * (double)wj[k];
+        }
+    }
+}
+
+/*
+ * Propagate the forward error bound through one layer (see the header):
+ *   e_out[r][j] = (1 + g) sum_k |w[j][k]| e_in[r][idx[j][k]] + g (sum_k |w[j][k] y_in[r][idx[j][k]]| + |b[j]|)
+ * y_in are the exact (double) activations entering the layer; e_in may be NULL (exact inputs).
+ */
+void orc_layer_bound(int64_t R, int32_t N, int32_t K, const int32_t *idx, const float *w, const float *b, double g,
+                     const double *y_in, const double *e_in, double *e_out, int nthreads)
+{
+    set_threads(nthreads);
+    int64_t r;
+#pragma omp parallel for schedule(static)
+    for (r = 0; r < R; ++r) {
+        const double *yi = y_in + r * (int64_t)N;
+        const double *ei = e_in ? e_in + r * (int64_t)N : NULL;
+        double *eo = e_out + r * (int64_t)N;
+        for (int32_t j = 0; j < N; ++j) {
+            const int32_t *ij = idx + (int64_t)j * K;
+            const float *wj = w + (int64_t)j * K;
+            double prop = 0.0, s = 0.0;
+            for (int32_t k = 0; k < K; ++k) {
+                double aw = fabs((double)wj[k]);
+                s += aw * fabs(yi[ij[k]]);
+                if (ei) prop += aw * ei[ij[k]];
+            }
+            s += fabs((double)b[j]);
+            eo[j] = (1.0 + g) * prop + g * s;
         }
     }
 }

@@ -1,0 +1,785 @@
+// Host side of the C ABI declared in include/sdnn.h: validation, workspace
+// layout, the three ways of running the layer chain (eager launches, one
+// explicitly built hipGraph, one persistent cooperative kernel), the backward
+// orchestration with checkpoint segments, and the tile autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <utility>
+#include <vector>
+
+#include "sdnn.h"
+#include "sdnn_internal.hpp"
+
+using namespace sdnn;
+
+namespace {
+
+thread_local std::string g_err;
+
+sdnn_status fail(sdnn_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return fail(SDNN_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+    } while (0)
+
+#define TRY(expr)                                  \
+    do {                                           \
+        sdnn_status s_ = (expr);                   \
+        if (s_ != SDNN_OK) return s_;              \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+constexpr int P_GROUPS = 64;                    // backward row groups (dW partials)
+constexpr int NBAR = BAR_WORDS;
+constexpr size_t LDS_BUDGET = 152 * 1024;       // dynamic LDS a layer tile may use
+constexpr int MSE_BLOCKS = 256;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+struct Layout {
+    size_t act = 0, list0 = 0, list1 = 0, alive = 0, cnt = 0, bar = 0, err = 0, flag = 0;
+    size_t tr_ptr = 0, tr_e = 0, seg = 0, gbuf0 = 0, gbuf1 = 0, pdw = 0, pdb = 0;
+    size_t total = 0;
+};
+
+bool trainable(const sdnn_desc& d) { return (d.flags & SDNN_TRAINABLE) != 0; }
+
+Layout make_layout(const sdnn_desc& d) {
+    Layout y;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1));
+        return o;
+    };
+    const size_t R = (size_t)std::max<int64_t>(d.max_rows, 1), N = d.n_neurons, L = d.n_layers;
+    y.act = take(R * N * 4);
+    y.list0 = take(R * 4);
+    y.list1 = take(R * 4);
+    y.alive = take(R * 4);
+    y.cnt = take((size_t)MAX_BATCHES * (L + 1) * 4);
+    y.bar = take(NBAR * 4);
+    y.err = take(64);
+    y.flag = take(64);
+    if (trainable(d)) {
+        y.tr_ptr = take(L * (N + 1) * 4);
+        y.tr_e = take(L * N * K * 4);
+        y.seg = take((size_t)(d.ckpt_every + 1) * R * N * 4);
+        y.gbuf0 = take(std::max<size_t>(R, 2) * N * 4);   // also create-time scratch for 2N ints
+        y.gbuf1 = take(R * N * 4);
+        y.pdw = take((size_t)P_GROUPS * N * K * 4);
+        y.pdb = take((size_t)P_GROUPS * N * 4);
+    }
+    y.total = off;
+    return y;
+}
+
+sdnn_status check_desc(const sdnn_desc* d) {
+    if (!d) return fail(SDNN_EINVAL, "desc is NULL");
+    if (d->k != K) return fail(SDNN_EUNSUPPORTED, "k = %d: only k = 32 inputs per neuron is supported", d->k);
+    if (d->n_neurons < 1 || d->n_neurons > (1 << 20)) return fail(SDNN_EINVAL, "n_neurons = %d out of [1, 2^20]", d->n_neurons);
+    if (d->n_layers < 1) return fail(SDNN_EINVAL, "n_layers = %d must be >= 1", d->n_layers);
+    if (d->n_neurons < K) return fail(SDNN_EINVAL, "n_neurons = %d < k: k distinct inputs impossible", d->n_neurons);
+    if (!(d->clamp > 0.f) || !std::isfinite(d->clamp)) return fail(SDNN_EINVAL, "clamp must be finite and > 0");
+    if (d->max_rows < 0 || d->max_rows > INT32_MAX) return fail(SDNN_EINVAL, "max_rows out of range");
+    if ((double)d->max_rows * d->n_neurons >= 9.0e15) return fail(SDNN_EINVAL, "max_rows * n_neurons too large");
+    if (trainable(*d)) {
+        if (d->ckpt_every < 1) return fail(SDNN_EINVAL, "SDNN_TRAINABLE needs ckpt_every >= 1");
+        if ((size_t)bwd_T() * d->n_neurons * 4 > LDS_BUDGET)
+            return fail(SDNN_EUNSUPPORTED, "backward supports n_neurons <= %zu", LDS_BUDGET / (bwd_T() * 4));
+    } else if (d->ckpt_every < 0) {
+        return fail(SDNN_EINVAL, "ckpt_every must be >= 0");
+    }
+    if (d->flags & ~(SDNN_TRAINABLE | SDNN_NO_COMPACTION | SDNN_DEBUG_CHECKS | SDNN_AUTOTUNE))
+        return fail(SDNN_EINVAL, "unknown flag bits 0x%x", d->flags);
+    return SDNN_OK;
+}
+
+// ---------------------------------------------------------------- launch records
+// A kernel launch with its arguments kept alive, so it can be issued eagerly or
+// recorded as a hipGraph kernel node.
+struct Launch {
+    virtual ~Launch() = default;
+    const void* fn = nullptr;
+    dim3 grid, block;
+    size_t shmem = 0;
+    bool cooperative = false;
+    std::vector<void*> ptrs;
+};
+
+template <typename... A>
+struct LaunchT : Launch {
+    std::tuple<A...> args;
+    explicit LaunchT(A... a) : args(a...) {
+        std::apply([this](auto&... x) { ptrs = {static_cast<void*>(&x)...}; }, args);
+    }
+};
+
+template <typename... A>
+std::unique_ptr<Launch> mk(const void* fn, dim3 grid, dim3 block, size_t shmem, A... a) {
+    auto p = std::make_unique<LaunchT<A...>>(a...);
+    p->fn = fn;
+    p->grid = grid;
+    p->block = block;
+    p->shmem = shmem;
+    return p;
+}
+
+using Plan = std::vector<std::unique_ptr<Launch>>;
+
+}  // namespace
+
+struct sdnn_net_s {
+    sdnn_desc d{};
+    const int32_t* idx = nullptr;
+    const float* w = nullptr;
+    const float* b = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout lay;
+    float* act = nullptr;
+    int32_t *list0 = nullptr, *list1 = nullptr, *alive = nullptr, *cnt = nullptr, *err = nullptr, *flag = nullptr;
+    unsigned* bar = nullptr;
+    int32_t *tr_ptr = nullptr, *tr_e = nullptr;
+    float *seg = nullptr, *gbuf0 = nullptr, *gbuf1 = nullptr, *pdw = nullptr, *pdb = nullptr;
+    bool compaction = true;
+    int exec = SDNN_EXEC_AUTO;
+    int variant = 0;
+    int grid = 0;
+    int chain_grid = 0;
+    float tuned_us = 0.f;
+    int num_cu = 0;
+    int device = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int64_t> gkey;
+};
+
+namespace {
+
+const FwdVariant& var(const sdnn_net_s* n) { return fwd_variant(n->variant); }
+
+bool variant_fits(const FwdVariant& v, int N) {
+    if (!v.staged) return true;
+    return (size_t)v.T * N * 4 <= LDS_BUDGET;
+}
+
+sdnn_status prepare_variant(sdnn_net_s* n, int vi, int* grid, int* chain_grid) {
+    const FwdVariant& v = fwd_variant(vi);
+    const size_t sh = fwd_lds_bytes(v, n->d.n_neurons);
+    HIPCHK(hipFuncSetAttribute(v.layer_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+    HIPCHK(hipFuncSetAttribute(v.chain_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+    int occ = 0, occc = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, v.layer_fn, v.NT, sh));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occc, v.chain_fn, v.NT, sh));
+    if (occ < 1 || occc < 1) return fail(SDNN_EUNSUPPORTED, "kernel variant T=%d NT=%d does not fit a CU", v.T, v.NT);
+    *grid = n->num_cu * occ;
+    *chain_grid = n->num_cu * occc;
+    return SDNN_OK;
+}
+
+// Default tile plan: the widest power-of-two row tile that fits the LDS budget.
+int default_variant(int N) {
+    int best = -1, bestT = 0;
+    for (int i = 0; i < fwd_variant_count(); ++i) {
+        const FwdVariant& v = fwd_variant(i);
+        if (!v.staged || !variant_fits(v, N) || v.T > 16) continue;
+        const int want_nt = v.T >= 16 ? 512 : 1024;
+        if (v.NT != want_nt) continue;
+        if (v.T > bestT) { bestT = v.T; best = i; }
+    }
+    if (best >= 0) return best;
+    for (int i = 0; i < fwd_variant_count(); ++i) {
+        const FwdVariant& v = fwd_variant(i);
+        if (!v.staged && v.T == 1 && v.NT == 1024) return i;
+    }
+    return 0;
+}
+
+sdnn_status issue(const Plan& plan, hipStream_t s) {
+    for (const auto& L : plan) {
+        if (L->cooperative) {
+            HIPCHK(hipLaunchCooperativeKernel(L->fn, L->grid, L->block, const_cast<void**>(L->ptrs.data()),
+                                              (unsigned)L->shmem, s));
+        } else {
+            HIPCHK(hipLaunchKernel(L->fn, L->grid, L->block, const_cast<void**>(L->ptrs.data()), L->shmem, s));
+        }
+    }
+    return SDNN_OK;
+}
+
+void drop_graph(sdnn_net_s* n) {
+    if (n->gexec) (void)hipGraphExecDestroy(n->gexec);
+    if (n->graph) (void)hipGraphDestroy(n->graph);
+    n->gexec = nullptr;
+    n->graph = nullptr;
+    n->gkey.clear();
+}
+
+sdnn_status build_graph(sdnn_net_s* n, const Plan& plan) {
+    drop_graph(n);
+    HIPCHK(hipGraphCreate(&n->graph, 0));
+    hipGraphNode_t prev = nullptr;
+    for (const auto& L : plan) {
+        hipKernelNodeParams p{};
+        p.func = const_cast<void*>(L->fn);
+        p.gridDim = L->grid;
+        p.blockDim = L->block;
+        p.sharedMemBytes = (unsigned)L->shmem;
+        p.kernelParams = const_cast<void**>(L->ptrs.data());
+        p.extra = nullptr;
+        hipGraphNode_t node;
+        HIPCHK(hipGraphAddKernelNode(&node, n->graph, prev ? &prev : nullptr, prev ? 1 : 0, &p));
+        prev = node;
+    }
+    HIPCHK(hipGraphInstantiate(&n->gexec, n->graph, nullptr, nullptr, 0));
+    return SDNN_OK;
+}
+
+LayerArgs layer_args_chain(const sdnn_net_s* n, int l, const float* y0, float* y_out, float* ckpt, int64_t rows,
+                           int32_t row_base, int32_t nb_rows, int32_t* cnt_region) {
+    const int L = n->d.n_layers, N = n->d.n_neurons, S = n->d.ckpt_every;
+    const size_t NK = (size_t)N * K;
+    const bool out_is_y = ((L - 1 - l) & 1) == 0;
+    const bool cmp = n->compaction;
+    LayerArgs a{};
+    a.yin = l == 0 ? y0 : (out_is_y ? n->act : y_out);
+    a.yout = out_is_y ? y_out : n->act;
+    a.ycopy = (ckpt && S > 0 && (l + 1) % S == 0 && l + 1 < L) ? ckpt + (size_t)((l + 1) / S - 1) * rows * N : nullptr;
+    a.yzero = (cmp && !out_is_y) ? y_out : nullptr;
+    a.idx = n->idx + l * NK;
+    a.w = n->w + l * NK;
+    a.b = n->b + (size_t)l * N;
+    a.list_in = (l == 0 || !cmp) ? nullptr : ((l & 1) ? n->list1 : n->list0);
+    a.list_out = cmp ? (((l + 1) & 1) ? n->list1 : n->list0) : nullptr;
+    a.cnt_in = (l == 0 || !cmp) ? nullptr : cnt_region + l;
+    a.cnt_out = cnt_region + l + 1;
+    a.alive = n->alive;
+    a.row_base = row_base;
+    a.nrows = nb_rows;
+    a.N = N;
+    a.layer = l;
+    a.clamp = n->d.clamp;
+    return a;
+}
+
+// The per-batch ("plain") chain: for each non-empty batch, an init node and L
+// layer nodes; then one finalize node.  Used eagerly or as one hipGraph.
+Plan plan_chain(const sdnn_net_s* n, const float* y0, int64_t rows, const int64_t* off, int nb, float* y_out,
+                int32_t* nz_rows, int32_t* n_nz, float* ckpt, int32_t* layer_rows) {
+    Plan p;
+    const int L = n->d.n_layers;
+    const FwdVariant& v = var(n);
+    const size_t sh = fwd_lds_bytes(v, n->d.n_neurons);
+    int region = 0;
+    for (int bi = 0; bi < nb; ++bi) {
+        const int32_t r0 = (int32_t)off[bi], nbr = (int32_t)(off[bi + 1] - off[bi]);
+        if (nbr == 0) continue;
+        int32_t* cr = n->cnt + (size_t)region * (L + 1);
+        p.push_back(mk((const void*)&k_chain_init, dim3(1), dim3(256), 0, cr, (int32_t)L, nbr,
+                       (int32_t)(n->compaction ? 1 : 0), (unsigned*)nullptr, (int32_t)0));
+        for (int l = 0; l < L; ++l) {
+            LayerArgs a = layer_args_chain(n, l, y0, y_out, ckpt, rows, r0, nbr, cr);
+            const int ntiles = (nbr + v.T - 1) / v.T;
+            const int g = std::max(1, std::min(n->grid, ntiles));
+            p.push_back(mk(v.layer_fn, dim3(g), dim3(v.NT), sh, a));
+        }
+        ++region;
+    }
+    p.push_back(mk((const void*)&k_finalize, dim3(1), dim3(1024), 0, (const int32_t*)n->alive, (int32_t)rows, nz_rows,
+                   n_nz, (const int32_t*)n->cnt, (int32_t)region, (int32_t)L, layer_rows));
+    return p;
+}
+
+// The merged chain: all batches' rows in one work list, one node per layer.
+Plan plan_merged(const sdnn_net_s* n, const float* y0, int64_t rows, float* y_out, int32_t* nz_rows, int32_t* n_nz,
+                 float* ckpt, int32_t* layer_rows) {
+    const int64_t off[2] = {0, rows};
+    return plan_chain(n, y0, rows, off, 1, y_out, nz_rows, n_nz, ckpt, layer_rows);
+}
+
+Plan plan_persistent(const sdnn_net_s* n, const float* y0, int64_t rows, float* y_out, int32_t* nz_rows,
+                     int32_t* n_nz, float* ckpt, int32_t* layer_rows) {
+    Plan p;
+    const int L = n->d.n_layers;
+    const FwdVariant& v = var(n);
+    const size_t sh = fwd_lds_bytes(v, n->d.n_neurons);
+    p.push_back(mk((const void*)&k_chain_init, dim3(1), dim3(256), 0, n->cnt, (int32_t)L, (int32_t)rows,
+                   (int32_t)(n->compaction ? 1 : 0), n->bar, (int32_t)NBAR));
+    ChainArgs c{};
+    c.y0 = y0;
+    c.y_out = y_out;
+    c.act = n->act;
+    c.ckpt = ckpt;
+    c.idx = n->idx;
+    c.w = n->w;
+    c.b = n->b;
+    c.list0 = n->list0;
+    c.list1 = n->list1;
+    c.cnt = n->cnt;
+    c.alive = n->alive;
+    c.bar = n->bar;
+    c.err = n->err;
+    c.rows = (int32_t)rows;
+    c.N = n->d.n_neurons;
+    c.L = L;
+    c.ckpt_every = n->d.ckpt_every > 0 ? n->d.ckpt_every : L + 1;
+    c.compaction = n->compaction ? 1 : 0;
+    c.clamp = n->d.clamp;
+    auto ch = mk(v.chain_fn, dim3(n->chain_grid), dim3(v.NT), sh, c);
+    ch->cooperative = true;
+    p.push_back(std::move(ch));
+    p.push_back(mk((const void*)&k_finalize, dim3(1), dim3(1024), 0, (const int32_t*)n->alive, (int32_t)rows, nz_rows,
+                   n_nz, (const int32_t*)n->cnt, (int32_t)1, (int32_t)L, layer_rows));
+    return p;
+}
+
+int blocks_for(int64_t n, int per = 256, int cap = 4096) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>(cap, (n + per - 1) / per));
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+const char* sdnn_last_error(void) { return g_err.c_str(); }
+
+const char* sdnn_version(void) { return "sdnn 0.1 (gfx950)"; }
+
+sdnn_status sdnn_workspace_size(const sdnn_desc* desc, size_t* bytes) {
+    TRY(check_desc(desc));
+    if (!bytes) return fail(SDNN_EINVAL, "bytes is NULL");
+    *bytes = make_layout(*desc).total;
+    return SDNN_OK;
+}
+
+sdnn_status sdnn_ckpt_size(const sdnn_desc* desc, int64_t rows, size_t* bytes) {
+    TRY(check_desc(desc));
+    if (!bytes || rows < 0) return fail(SDNN_EINVAL, "bad arguments");
+    const int S = desc->ckpt_every;
+    if (S < 1) {
+        *bytes = 0;
+        return SDNN_OK;
+    }
+    const int64_t slots = (desc->n_layers + S - 1) / S - 1;
+    *bytes = (size_t)std::max<int64_t>(slots, 0) * (size_t)rows * desc->n_neurons * 4;
+    return SDNN_OK;
+}
+
+sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* w, const float* bias, void* workspace,
+                        size_t ws_bytes, void* stream, sdnn_net* out) {
+    TRY(check_desc(desc));
+    if (!out) return fail(SDNN_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!idx || !w || !bias) return fail(SDNN_EINVAL, "idx, w and bias must be device pointers");
+    if (((uintptr_t)idx | (uintptr_t)w) & 15) return fail(SDNN_EINVAL, "idx and w must be 16-byte aligned");
+    const Layout lay = make_layout(*desc);
+    if (!workspace) return fail(SDNN_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace % ALIGN) return fail(SDNN_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < lay.total) return fail(SDNN_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, lay.total);
+    hipStream_t s = (hipStream_t)stream;
+
+    auto n = std::make_unique<sdnn_net_s>();
+    n->d = *desc;
+    n->idx = idx;
+    n->w = w;
+    n->b = bias;
+    n->ws = (char*)workspace;
+    n->ws_bytes = ws_bytes;
+    n->lay = lay;
+    n->act = (float*)(n->ws + lay.act);
+    n->list0 = (int32_t*)(n->ws + lay.list0);
+    n->list1 = (int32_t*)(n->ws + lay.list1);
+    n->alive = (int32_t*)(n->ws + lay.alive);
+    n->cnt = (int32_t*)(n->ws + lay.cnt);
+    n->bar = (unsigned*)(n->ws + lay.bar);
+    n->err = (int32_t*)(n->ws + lay.err);
+    n->flag = (int32_t*)(n->ws + lay.flag);
+    if (trainable(*desc)) {
+        n->tr_ptr = (int32_t*)(n->ws + lay.tr_ptr);
+        n->tr_e = (int32_t*)(n->ws + lay.tr_e);
+        n->seg = (float*)(n->ws + lay.seg);
+        n->gbuf0 = (float*)(n->ws + lay.gbuf0);
+        n->gbuf1 = (float*)(n->ws + lay.gbuf1);
+        n->pdw = (float*)(n->ws + lay.pdw);
+        n->pdb = (float*)(n->ws + lay.pdb);
+    }
+    HIPCHK(hipGetDevice(&n->device));
+    HIPCHK(hipDeviceGetAttribute(&n->num_cu, hipDeviceAttributeMultiprocessorCount, n->device));
+
+    const int N = desc->n_neurons, L = desc->n_layers;
+    const int64_t nnz = (int64_t)N * K * L;
+    // error word, flags, barrier words
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, n->err, (int64_t)16, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, n->flag, (int64_t)16, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(2), dim3(256), 0, s, (int32_t*)n->bar, (int64_t)NBAR, 0);
+    HIPCHK(hipGetLastError());
+    if (desc->flags & SDNN_DEBUG_CHECKS) {
+        hipLaunchKernelGGL(k_check_params, dim3(blocks_for((int64_t)N * L)), dim3(256), 0, s, idx, w, bias, N, L,
+                           n->flag, (float*)nullptr);
+        HIPCHK(hipGetLastError());
+        int32_t bad = 0;
+        HIPCHK(hipMemcpyAsync(&bad, n->flag, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (bad)
+            return fail(SDNN_EINVAL, "parameter check failed:%s%s%s%s", (bad & 1) ? " idx out of range;" : "",
+                        (bad & 2) ? " idx not strictly ascending;" : "", (bad & 4) ? " non-finite weight;" : "",
+                        (bad & 8) ? " non-finite bias;" : "");
+    }
+    // Compaction is exact only while every bias is <= 0.
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, n->flag + 1, (int64_t)1, 0);
+    hipLaunchKernelGGL(k_max_bias, dim3(blocks_for((int64_t)N * L)), dim3(256), 0, s, bias, (int64_t)N * L, n->flag + 1);
+    HIPCHK(hipGetLastError());
+    int32_t pos = 0;
+    HIPCHK(hipMemcpyAsync(&pos, n->flag + 1, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    n->compaction = !(desc->flags & SDNN_NO_COMPACTION) && pos == 0;
+
+    if (trainable(*desc)) {
+        // transposed pattern per layer: counting sort of edge positions by input id
+        int32_t* deg = (int32_t*)n->gbuf0;
+        int32_t* cursor = deg + N;
+        for (int l = 0; l < L; ++l) {
+            const int32_t* il = idx + (size_t)l * N * K;
+            int32_t* ptr = n->tr_ptr + (size_t)l * (N + 1);
+            int32_t* te = n->tr_e + (size_t)l * N * K;
+            hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(2 * N)), dim3(256), 0, s, deg, (int64_t)2 * N, 0);
+            hipLaunchKernelGGL(k_tr_count, dim3(blocks_for((int64_t)N * K)), dim3(256), 0, s, il, (int64_t)N * K, deg);
+            hipLaunchKernelGGL(k_tr_scan, dim3(1), dim3(1024), 0, s, (const int32_t*)deg, N, ptr);
+            hipLaunchKernelGGL(k_tr_fill, dim3(blocks_for((int64_t)N * K)), dim3(256), 0, s, il, (int64_t)N * K,
+                               (const int32_t*)ptr, cursor, te);
+            hipLaunchKernelGGL(k_tr_sort, dim3(blocks_for(N)), dim3(256), 0, s, (const int32_t*)ptr, N, te);
+        }
+        HIPCHK(hipGetLastError());
+        const size_t bsh = (size_t)bwd_T() * N * 4;
+        HIPCHK(hipFuncSetAttribute(bwd_dw_fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bsh));
+        HIPCHK(hipFuncSetAttribute(bwd_dy_fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bsh));
+    }
+    (void)nnz;
+    n->variant = default_variant(N);
+    TRY(prepare_variant(n.get(), n->variant, &n->grid, &n->chain_grid));
+    HIPCHK(hipStreamSynchronize(s));
+    sdnn_net net = n.release();
+    if (desc->flags & SDNN_AUTOTUNE) {
+        const sdnn_status st = sdnn_tune(net, desc->max_rows, stream);
+        if (st != SDNN_OK) {
+            sdnn_destroy(net);
+            return st;
+        }
+    }
+    *out = net;
+    return SDNN_OK;
+}
+
+sdnn_status sdnn_set_exec(sdnn_net net, int32_t mode) {
+    if (!net) return fail(SDNN_EINVAL, "net is NULL");
+    if (mode < SDNN_EXEC_AUTO || mode > SDNN_EXEC_GRAPH_MERGED) return fail(SDNN_EINVAL, "unknown exec mode %d", mode);
+    net->exec = mode;
+    return SDNN_OK;
+}
+
+sdnn_status sdnn_get_plan(sdnn_net net, sdnn_plan* plan) {
+    if (!net || !plan) return fail(SDNN_EINVAL, "NULL argument");
+    const FwdVariant& v = var(net);
+    plan->rows_per_tile = v.T;
+    plan->threads = v.NT;
+    plan->grid = net->grid;
+    plan->variant = v.staged ? 0 : 1;
+    plan->tuned_us = net->tuned_us;
+    return SDNN_OK;
+}
+
+sdnn_status sdnn_tune(sdnn_net net, int64_t rows, void* stream) {
+    if (!net) return fail(SDNN_EINVAL, "net is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const int N = net->d.n_neurons;
+    const int64_t rt = std::min<int64_t>(rows, net->d.max_rows / 2);
+    if (rt < 1) return SDNN_OK;   // nothing to time with
+    float* in = net->act;
+    float* outb = net->act + (size_t)rt * N;
+    hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for(rt * N)), dim3(256), 0, s, in, rt * N, 1.0f);
+    HIPCHK(hipGetLastError());
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_v = net->variant, best_g = net->grid, best_cg = net->chain_grid;
+    for (int vi = 0; vi < fwd_variant_count(); ++vi) {
+        const FwdVariant& v = fwd_variant(vi);
+        if (!variant_fits(v, N)) continue;
+        int g = 0, cg = 0;
+        if (prepare_variant(net, vi, &g, &cg) != SDNN_OK) continue;
+        LayerArgs a{};
+        a.yin = in;
+        a.yout = outb;
+        a.idx = net->idx;
+        a.w = net->w;
+        a.b = net->b;
+        a.nrows = (int32_t)rt;
+        a.N = N;
+        a.clamp = net->d.clamp;
+        const int gg = std::max(1, std::min<int>(g, (int)((rt + v.T - 1) / v.T)));
+        void* args[] = {&a};
+        const size_t sh = fwd_lds_bytes(v, N);
+        HIPCHK(hipLaunchKernel(v.layer_fn, dim3(gg), dim3(v.NT), args, sh, s));
+        HIPCHK(hipEventRecord(e0, s));
+        const int reps = 3;
+        for (int r = 0; r < reps; ++r) HIPCHK(hipLaunchKernel(v.layer_fn, dim3(gg), dim3(v.NT), args, sh, s));
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        const float us = ms * 1000.f / reps;
+        if (us < best) {
+            best = us;
+            best_v = vi;
+            best_g = g;
+            best_cg = cg;
+        }
+    }
+    HIPCHK(hipEventDestroy(e0));
+    HIPCHK(hipEventDestroy(e1));
+    net->variant = best_v;
+    net->grid = best_g;
+    net->chain_grid = best_cg;
+    net->tuned_us = best < 1e29f ? best : 0.f;
+    drop_graph(net);
+    return SDNN_OK;
+}
+
+sdnn_status sdnn_forward(sdnn_net net, const float* y0, int64_t rows, const int64_t* batch_off, int32_t n_batches,
+                         float* y_out, int32_t* nz_rows, int32_t* n_nz, float* ckpt, int32_t* layer_rows,
+                         void* stream) {
+    if (!net) return fail(SDNN_EINVAL, "net is NULL");
+    const sdnn_desc& d = net->d;
+    if (rows < 0 || rows > d.max_rows) return fail(SDNN_EINVAL, "rows = %lld outside [0, max_rows = %lld]",
+                                                  (long long)rows, (long long)d.max_rows);
+    if (!n_nz || !nz_rows) return fail(SDNN_EINVAL, "nz_rows and n_nz are required");
+    if (rows > 0 && (!y0 || !y_out)) return fail(SDNN_EINVAL, "y0 and y_out are required");
+    const size_t bytes = (size_t)rows * d.n_neurons * 4;
+    if (rows > 0 && (const char*)y0 < (const char*)y_out + bytes && (const char*)y_out < (const char*)y0 + bytes)
+        return fail(SDNN_EINVAL, "y0 and y_out overlap");
+    if (ckpt && d.ckpt_every < 1) return fail(SDNN_EINVAL, "ckpt given but the net has ckpt_every = 0");
+    std::vector<int64_t> off;
+    if (batch_off) {
+        if (n_batches < 1 || n_batches > MAX_BATCHES)
+            return fail(SDNN_EINVAL, "n_batches = %d outside [1, %d]", n_batches, MAX_BATCHES);
+        off.assign(batch_off, batch_off + n_batches + 1);
+        if (off[0] != 0 || off[n_batches] != rows) return fail(SDNN_EINVAL, "batch offsets must run from 0 to rows");
+        for (int i = 0; i < n_batches; ++i)
+            if (off[i + 1] < off[i]) return fail(SDNN_EINVAL, "batch offsets must be non-decreasing");
+    } else {
+        off = {0, rows};
+        n_batches = 1;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int L = d.n_layers;
+    if (rows == 0) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, n_nz, (int64_t)1, 0);
+        if (layer_rows) hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(L + 1)), dim3(256), 0, s, layer_rows, (int64_t)L + 1, 0);
+        HIPCHK(hipGetLastError());
+        return SDNN_OK;
+    }
+    int mode = net->exec;
+    if (mode == SDNN_EXEC_AUTO) mode = n_batches > 1 ? SDNN_EXEC_GRAPH_MERGED : SDNN_EXEC_GRAPH;
+    if (mode == SDNN_EXEC_PERSISTENT) {
+        Plan p = plan_persistent(net, y0, rows, y_out, nz_rows, n_nz, ckpt, layer_rows);
+        return issue(p, s);
+    }
+    // GRAPH / EAGER: batches one after another; GRAPH_MERGED: one chain over all rows.
+    const bool merged = mode == SDNN_EXEC_GRAPH_MERGED;
+    if (mode == SDNN_EXEC_EAGER) {
+        Plan p = merged ? plan_merged(net, y0, rows, y_out, nz_rows, n_nz, ckpt, layer_rows)
+                        : plan_chain(net, y0, rows, off.data(), n_batches, y_out, nz_rows, n_nz, ckpt, layer_rows);
+        return issue(p, s);
+    }
+    std::vector<int64_t> key = {(int64_t)(uintptr_t)y0, (int64_t)(uintptr_t)y_out, (int64_t)(uintptr_t)nz_rows,
+                                (int64_t)(uintptr_t)n_nz, (int64_t)(uintptr_t)ckpt, (int64_t)(uintptr_t)layer_rows,
+                                rows, net->variant, net->grid, merged ? 1 : 0};
+    key.insert(key.end(), off.begin(), off.end());
+    if (!net->gexec || key != net->gkey) {
+        Plan p = merged ? plan_merged(net, y0, rows, y_out, nz_rows, n_nz, ckpt, layer_rows)
+                        : plan_chain(net, y0, rows, off.data(), n_batches, y_out, nz_rows, n_nz, ckpt, layer_rows);
+        TRY(build_graph(net, p));
+        net->gkey = key;
+    }
+    HIPCHK(hipGraphLaunch(net->gexec, s));
+    return SDNN_OK;
+}
+
+sdnn_status sdnn_layer(sdnn_net net, int32_t layer, const float* y_in, int64_t rows, float* y_out, void* stream) {
+    if (!net) return fail(SDNN_EINVAL, "net is NULL");
+    const sdnn_desc& d = net->d;
+    if (layer < 0 || layer >= d.n_layers) return fail(SDNN_EINVAL, "layer %d out of range", layer);
+    if (rows < 0 || rows > INT32_MAX) return fail(SDNN_EINVAL, "rows out of range");
+    if (rows == 0) return SDNN_OK;
+    if (!y_in || !y_out) return fail(SDNN_EINVAL, "y_in and y_out are required");
+    const size_t bytes = (size_t)rows * d.n_neurons * 4;
+    if ((const char*)y_in < (const char*)y_out + bytes && (const char*)y_out < (const char*)y_in + bytes)
+        return fail(SDNN_EINVAL, "y_in and y_out overlap");
+    const FwdVariant& v = var(net);
+    const size_t NK = (size_t)d.n_neurons * K;
+    LayerArgs a{};
+    a.yin = y_in;
+    a.yout = y_out;
+    a.idx = net->idx + layer * NK;
+    a.w = net->w + layer * NK;
+    a.b = net->b + (size_t)layer * d.n_neurons;
+    a.nrows = (int32_t)rows;
+    a.N = d.n_neurons;
+    a.layer = layer;
+    a.clamp = d.clamp;
+    const int g = std::max(1, std::min<int>(net->grid, (int)((rows + v.T - 1) / v.T)));
+    void* args[] = {&a};
+    HIPCHK(hipLaunchKernel(v.layer_fn, dim3(g), dim3(v.NT), args, fwd_lds_bytes(v, d.n_neurons), (hipStream_t)stream));
+    return SDNN_OK;
+}
+
+sdnn_status sdnn_backward(sdnn_net net, const float* y0, int64_t rows, const float* ckpt, const int32_t* nz_rows,
+                          const int32_t* n_nz, const float* dy_out, float* dw, float* dbias, float* dy0,
+                          void* stream) {
+    if (!net) return fail(SDNN_EINVAL, "net is NULL");
+    const sdnn_desc& d = net->d;
+    if (!trainable(d)) return fail(SDNN_EINVAL, "net was not created with SDNN_TRAINABLE");
+    if (rows < 0 || rows > d.max_rows) return fail(SDNN_EINVAL, "rows out of range");
+    if (!nz_rows || !n_nz || !dw || !dbias) return fail(SDNN_EINVAL, "nz_rows, n_nz, dw and dbias are required");
+    const int L = d.n_layers, N = d.n_neurons, S = d.ckpt_every;
+    const int nseg = (L + S - 1) / S;
+    if (rows > 0 && (!y0 || !dy_out)) return fail(SDNN_EINVAL, "y0 and dy_out are required");
+    if (rows > 0 && nseg > 1 && !ckpt) return fail(SDNN_EINVAL, "ckpt is required when n_layers > ckpt_every");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t NK = (size_t)N * K;
+    if (dy0) {
+        hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for((int64_t)rows * N)), dim3(256), 0, s, dy0, (int64_t)rows * N, 0.f);
+    }
+    if (rows == 0) {
+        hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for((int64_t)L * NK)), dim3(256), 0, s, dw, (int64_t)L * NK, 0.f);
+        hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for((int64_t)L * N)), dim3(256), 0, s, dbias, (int64_t)L * N, 0.f);
+        HIPCHK(hipGetLastError());
+        return SDNN_OK;
+    }
+    const size_t RN = (size_t)d.max_rows * N;
+    auto seg = [&](int i) { return net->seg + (size_t)i * RN; };
+    float* D = net->gbuf0;
+    float* Dn = net->gbuf1;
+    const int gather_grid = std::min<int64_t>(rows, 8192);
+    hipLaunchKernelGGL(k_gather_rows, dim3(gather_grid), dim3(256), 0, s, dy_out, nz_rows, n_nz, N, D);
+    const FwdVariant& v = var(net);
+    const size_t fsh = fwd_lds_bytes(v, N);
+    const int fgrid = std::max(1, std::min<int>(net->grid, (int)((rows + v.T - 1) / v.T)));
+    const size_t bsh = (size_t)bwd_T() * N * 4;
+    const int dy_grid = std::max(1, std::min<int>(net->num_cu * 2, (int)((rows + bwd_T() - 1) / bwd_T())));
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+        const int l0 = sg * S, l1 = std::min(L, l0 + S);
+        const float* src = sg == 0 ? y0 : ckpt + (size_t)(sg - 1) * rows * N;
+        hipLaunchKernelGGL(k_gather_rows, dim3(gather_grid), dim3(256), 0, s, src, nz_rows, n_nz, N, seg(0));
+        for (int l = l0; l < l1; ++l) {
+            LayerArgs a{};
+            a.yin = seg(l - l0);
+            a.yout = seg(l - l0 + 1);
+            a.idx = net->idx + l * NK;
+            a.w = net->w + l * NK;
+            a.b = net->b + (size_t)l * N;
+            a.cnt_in = n_nz;
+            a.N = N;
+            a.layer = l;
+            a.clamp = d.clamp;
+            void* args[] = {&a};
+            HIPCHK(hipLaunchKernel(v.layer_fn, dim3(fgrid), dim3(v.NT), args, fsh, s));
+        }
+        for (int l = l1 - 1; l >= l0; --l) {
+            BwdDwArgs da{};
+            da.y_in = seg(l - l0);
+            da.y_out = seg(l - l0 + 1);
+            da.dy = D;
+            da.idx = net->idx + l * NK;
+            da.nrows = n_nz;
+            da.pdw = net->pdw;
+            da.pdb = net->pdb;
+            da.N = N;
+            da.P = P_GROUPS;
+            da.clamp = d.clamp;
+            void* dargs[] = {&da};
+            HIPCHK(hipLaunchKernel(bwd_dw_fn(), dim3(P_GROUPS, (N + bwd_threads() - 1) / bwd_threads()),
+                                   dim3(bwd_threads()), dargs, bsh, s));
+            hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for((int64_t)NK + N)), dim3(256), 0, s,
+                               (const float*)net->pdw, (const float*)net->pdb, (int32_t)P_GROUPS, (int32_t)N,
+                               dw + (size_t)l * NK, dbias + (size_t)l * N);
+            if (l > 0 || dy0) {
+                BwdDyArgs ya{};
+                ya.y_out = seg(l - l0 + 1);
+                ya.dy = D;
+                ya.tr_ptr = net->tr_ptr + (size_t)l * (N + 1);
+                ya.tr_e = net->tr_e + (size_t)l * NK;
+                ya.w = net->w + l * NK;
+                ya.nrows = n_nz;
+                ya.rows_out = l == 0 ? nz_rows : nullptr;
+                ya.dy_in = l == 0 ? dy0 : Dn;
+                ya.N = N;
+                ya.clamp = d.clamp;
+                void* yargs[] = {&ya};
+                HIPCHK(hipLaunchKernel(bwd_dy_fn(), dim3(dy_grid), dim3(bwd_threads()), yargs, bsh, s));
+                std::swap(D, Dn);
+            }
+        }
+    }
+    HIPCHK(hipGetLastError());
+    return SDNN_OK;
+}
+
+sdnn_status sdnn_mse(const float* y, const float* t, int64_t n, float* dy, float* loss, void* stream) {
+    if (n < 0) return fail(SDNN_EINVAL, "n < 0");
+    if (n > 0 && (!y || !t)) return fail(SDNN_EINVAL, "y and t are required");
+    if (!dy && !loss) return SDNN_OK;
+    hipStream_t s = (hipStream_t)stream;
+    // loss[1 .. MSE_BLOCKS] are scratch for the per-block partial sums
+    float* partial = loss ? loss + 1 : nullptr;
+    if (!loss) {
+        hipLaunchKernelGGL(k_mse, dim3(MSE_BLOCKS), dim3(256), 0, s, y, t, n, dy, (float*)nullptr, n ? 2.f / (float)n : 0.f);
+    } else {
+        hipLaunchKernelGGL(k_mse, dim3(MSE_BLOCKS), dim3(256), 0, s, y, t, n, dy, partial, n ? 2.f / (float)n : 0.f);
+        hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, s, (const float*)partial, (int32_t)MSE_BLOCKS, loss,
+                           n ? 1.f / (float)n : 0.f);
+    }
+    HIPCHK(hipGetLastError());
+    return SDNN_OK;
+}
+
+sdnn_status sdnn_check_device(sdnn_net net, void* stream) {
+    if (!net) return fail(SDNN_EINVAL, "net is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    int32_t e = 0;
+    HIPCHK(hipMemcpyAsync(&e, net->err, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (e == DEV_BARRIER_TIMEOUT) return fail(SDNN_EDEVICE, "a persistent-kernel grid barrier timed out");
+    if (e != 0) return fail(SDNN_EDEVICE, "device error %d", e);
+    return SDNN_OK;
+}
+
+void sdnn_destroy(sdnn_net net) {
+    if (!net) return;
+    drop_graph(net);
+    delete net;
+}
+
+}  // extern "C"

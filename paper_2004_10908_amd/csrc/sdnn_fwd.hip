@@ -1,0 +1,406 @@
+// Forward kernels of the layered sparse DNN for gfx950.
+//
+// One layer (paper, section "Large Sparse Neural Network Inference"; the layer
+// rule of the challenge it runs):  y_{l+1}[r][j] = min(c, max(0, sum_k w[j][k] *
+// y_l[r][idx[j][k]] + b[j])) for every alive row r and neuron j.
+//
+// Work decomposition: a workgroup owns a tile of T activation rows and computes
+// all N outputs of those rows, so it alone decides whether each row is still
+// alive (has a nonzero) after the layer.  The T input rows are staged in LDS in
+// an interleaved [N][T] layout: the T values a neuron needs for one input id are
+// contiguous, so one gather is a single 16-byte (or 8/4-byte) LDS read serving T
+// rows.  Each lane owns one output neuron at a time, reads its 32 (id, weight)
+// pairs with 16-byte global loads and keeps T fp32 accumulators.  The sum runs
+// over the slots in ascending order with fused multiply-adds, then adds the bias.
+//
+// Compaction: rows that come out all-zero are dropped from the next layer's work
+// list (an all-zero row stays all-zero while every bias is <= 0).  A workgroup
+// ORs per-lane row bits with cross-lane shuffles, reserves list slots with one
+// atomic per tile and appends its alive rows.  Row values never move; only the
+// list of row ids shrinks.  The order of the list depends on atomic order, but a
+// row's arithmetic does not depend on its position, so outputs are bitwise
+// deterministic.  Once a layer's list is empty every later layer returns at once
+// (early exit), the GPU counterpart of the paper's condition-task loop that
+// stops dispatching.
+#include "sdnn_internal.hpp"
+
+namespace sdnn {
+
+__device__ __forceinline__ int ld_acquire(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int T>
+__device__ __forceinline__ void gather_fma(const float* __restrict__ lds, int i, float w, float (&acc)[T]) {
+    const float* p = lds + i * T;
+    if constexpr (T == 1) {
+        acc[0] = fmaf(w, p[0], acc[0]);
+    } else if constexpr (T == 2) {
+        const float2 v = *reinterpret_cast<const float2*>(p);
+        acc[0] = fmaf(w, v.x, acc[0]);
+        acc[1] = fmaf(w, v.y, acc[1]);
+    } else {
+#pragma unroll
+        for (int h = 0; h < T / 4; ++h) {
+            const float4 v = reinterpret_cast<const float4*>(p)[h];
+            acc[4 * h + 0] = fmaf(w, v.x, acc[4 * h + 0]);
+            acc[4 * h + 1] = fmaf(w, v.y, acc[4 * h + 1]);
+            acc[4 * h + 2] = fmaf(w, v.z, acc[4 * h + 2]);
+            acc[4 * h + 3] = fmaf(w, v.w, acc[4 * h + 3]);
+        }
+    }
+}
+
+// Direct variant: the T rows are read from global memory (rows too wide for LDS).
+template <int T>
+__device__ __forceinline__ void gather_fma_direct(const float* const (&yr)[T], int i, float w, float (&acc)[T]) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] = fmaf(w, yr[t][i], acc[t]);
+}
+
+// Unroll of the slot loop (4 slots per step): enough independent LDS reads in
+// flight to cover latency without exceeding the VGPR budget of NT threads per CU.
+template <int T, int NT>
+constexpr int slot_unroll() {
+    constexpr int budget = NT <= 256 ? 200 : (NT <= 512 ? 160 : 96);
+    constexpr int per_step = 8 + 4 * T;
+    constexpr int u = (budget - 3 * T) / per_step;
+    return u < 1 ? 1 : (u > 8 ? 8 : u);
+}
+
+// All tiles of one layer handled by workgroup `wg` of `nwg` (grid-stride).
+template <int T, int NT, bool STAGED>
+__device__ __forceinline__ void run_layer(const LayerArgs& a, float* __restrict__ lds, int wg, int nwg, int R) {
+    __shared__ int32_t s_rows[T];
+    __shared__ unsigned s_alive;
+    constexpr int UQ = slot_unroll<T, NT>();
+    const int N = a.N;
+    const int tid = threadIdx.x;
+    const int ntiles = (R + T - 1) / T;
+    for (int tile = wg; tile < ntiles; tile += nwg) {
+        if (tid < T) {
+            const int p = tile * T + tid;
+            s_rows[tid] = p < R ? (a.list_in ? a.list_in[p] : a.row_base + p) : -1;
+        }
+        if (tid == 0) s_alive = 0u;
+        __syncthreads();
+        int rr[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) rr[t] = s_rows[t];
+        if constexpr (STAGED) {
+            // interleaved [N][T] staging: consecutive threads fill consecutive LDS words
+            for (int e = tid; e < T * N; e += NT) {
+                const int t = e % T;
+                const int i = e / T;
+                const int r = s_rows[t];
+                lds[e] = r >= 0 ? a.yin[(size_t)r * N + i] : 0.f;
+            }
+            __syncthreads();
+        }
+        const float* yr[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) yr[t] = a.yin + (size_t)(rr[t] >= 0 ? rr[t] : 0) * N;
+        unsigned bits = 0u;
+        for (int j = tid; j < N; j += NT) {
+            float acc[T];
+#pragma unroll
+            for (int t = 0; t < T; ++t) acc[t] = 0.f;
+            const int4* ip = reinterpret_cast<const int4*>(a.idx + (size_t)j * K);
+            const float4* wp = reinterpret_cast<const float4*>(a.w + (size_t)j * K);
+#pragma unroll UQ
+            for (int q = 0; q < K / 4; ++q) {
+                const int4 iv = ip[q];
+                const float4 wv = wp[q];
+                if constexpr (STAGED) {
+                    gather_fma<T>(lds, iv.x, wv.x, acc);
+                    gather_fma<T>(lds, iv.y, wv.y, acc);
+                    gather_fma<T>(lds, iv.z, wv.z, acc);
+                    gather_fma<T>(lds, iv.w, wv.w, acc);
+                } else {
+                    gather_fma_direct<T>(yr, iv.x, wv.x, acc);
+                    gather_fma_direct<T>(yr, iv.y, wv.y, acc);
+                    gather_fma_direct<T>(yr, iv.z, wv.z, acc);
+                    gather_fma_direct<T>(yr, iv.w, wv.w, acc);
+                }
+            }
+            const float bj = a.b[j];
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const float y = fminf(fmaxf(acc[t] + bj, 0.f), a.clamp);
+                if (rr[t] >= 0) {
+                    const size_t o = (size_t)rr[t] * N + j;
+                    a.yout[o] = y;
+                    if (a.ycopy) a.ycopy[o] = y;
+                }
+                bits |= (y != 0.f ? 1u : 0u) << t;
+            }
+        }
+        // row liveness: OR over every neuron of the tile
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) bits |= __shfl_xor(bits, off);
+        if ((tid & 63) == 0 && bits) atomicOr(&s_alive, bits);
+        __syncthreads();
+        const unsigned alive = s_alive;
+        if (tid == 0 && a.list_out) {
+            int n = 0;
+#pragma unroll
+            for (int t = 0; t < T; ++t) n += (rr[t] >= 0 && ((alive >> t) & 1u)) ? 1 : 0;
+            if (n) {
+                int base = atomicAdd(a.cnt_out, n);
+#pragma unroll
+                for (int t = 0; t < T; ++t)
+                    if (rr[t] >= 0 && ((alive >> t) & 1u)) a.list_out[base++] = rr[t];
+            }
+        }
+        if (a.alive && tid < T) {
+            const int r = s_rows[tid];
+            if (r >= 0) a.alive[r] = (int32_t)((alive >> tid) & 1u);
+        }
+        if (a.yzero) {
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                if (rr[t] >= 0 && !((alive >> t) & 1u)) {
+                    float* z = a.yzero + (size_t)rr[t] * N;
+                    for (int i = tid; i < N; i += NT) z[i] = 0.f;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int T, int NT, bool STAGED>
+__global__ __launch_bounds__(NT) void k_layer(LayerArgs a) {
+    extern __shared__ __align__(16) float lds[];
+    const int R = a.cnt_in ? *a.cnt_in : a.nrows;
+    run_layer<T, NT, STAGED>(a, lds, blockIdx.x, gridDim.x, R);
+}
+
+// ---------------------------------------------------------------- grid barrier
+// Two-level arrive counter: workgroups arrive on one of 8 group counters
+// (blockIdx % 8, the XCD a workgroup is dispatched to), the last of each group
+// arrives on the root, the last at the root bumps the generation word that every
+// workgroup polls.  Counters return to zero after each barrier.  Waits are
+// bounded by the 100 MHz real-time counter; a time-out, or an error raised by
+// any other workgroup, makes every waiter leave with `false`.
+// bar layout (one 128-byte line each): [g*32] group g, [8*32] root, [9*32] generation.
+
+
+__device__ bool grid_barrier(unsigned* bar, unsigned& gen, int32_t* err) {
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned nwg = gridDim.x;
+        const unsigned g = blockIdx.x & 7u;
+        const unsigned ngroups = nwg < 8u ? nwg : 8u;
+        const unsigned gsize = (nwg - g + 7u) / 8u;
+        const unsigned target = gen + 1u;
+        int ok = 1;
+        __threadfence();
+        const unsigned old = atomicAdd(&bar[g * 32], 1u);
+        if (old == gsize - 1u) {
+            atomicExch(&bar[g * 32], 0u);
+            const unsigned o2 = atomicAdd(&bar[8 * 32], 1u);
+            if (o2 == ngroups - 1u) {
+                atomicExch(&bar[8 * 32], 0u);
+                __threadfence();
+                atomicExch(&bar[9 * 32], target);
+            }
+        }
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        while (__hip_atomic_load(&bar[9 * 32], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = 0; break; }
+            if (__builtin_amdgcn_s_memrealtime() - t0 > 1000000000ull) {   // 10 s at 100 MHz
+                atomicExch(err, (int32_t)DEV_BARRIER_TIMEOUT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __threadfence();
+        gen = target;
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// ---------------------------------------------------------------- finalize
+// Ascending ids of rows whose final activations are nonzero, and the per-layer
+// row profile.  One workgroup of 1024 threads: each thread counts a contiguous
+// segment of rows, an exclusive scan gives each segment its output offset.
+constexpr int FIN_NT = 1024;
+
+__device__ void finalize_body(const int32_t* alive, int32_t rows, int32_t* nz_rows, int32_t* n_nz, const int32_t* cnt,
+                              int32_t n_regions, int32_t L, int32_t* layer_rows) {
+    __shared__ int32_t s_scan[FIN_NT];
+    const int tid = threadIdx.x;
+    const int seg = (rows + FIN_NT - 1) / FIN_NT;
+    const int r0 = min(rows, tid * seg), r1 = min(rows, r0 + seg);
+    int c = 0;
+    for (int r = r0; r < r1; ++r) c += alive[r] != 0;
+    s_scan[tid] = c;
+    __syncthreads();
+    for (int off = 1; off < FIN_NT; off <<= 1) {
+        const int v = tid >= off ? s_scan[tid - off] : 0;
+        __syncthreads();
+        s_scan[tid] += v;
+        __syncthreads();
+    }
+    int pos = s_scan[tid] - c;
+    for (int r = r0; r < r1; ++r)
+        if (alive[r] != 0) nz_rows[pos++] = r;
+    const int total = s_scan[FIN_NT - 1];
+    if (tid == 0) *n_nz = total;
+    if (layer_rows) {
+        for (int l = tid; l < L; l += FIN_NT) {
+            int s = 0;
+            for (int g = 0; g < n_regions; ++g) s += cnt[(size_t)g * (L + 1) + l];
+            layer_rows[l] = s;
+        }
+        if (tid == 0) layer_rows[L] = total;
+    }
+}
+
+__global__ __launch_bounds__(FIN_NT) void k_finalize(const int32_t* alive, int32_t rows, int32_t* nz_rows,
+                                                     int32_t* n_nz, const int32_t* cnt, int32_t n_regions, int32_t L,
+                                                     int32_t* layer_rows) {
+    finalize_body(alive, rows, nz_rows, n_nz, cnt, n_regions, L, layer_rows);
+}
+
+// ---------------------------------------------------------------- persistent chain
+// All layers in one cooperative launch: layer l's tiles are spread over the
+// co-resident grid, a grid barrier separates layers, and the loop stops as soon
+// as a layer's work list is empty.  Layer l writes X_l, which is y_out when
+// (L-1-l) is even and the workspace buffer otherwise, so the last layer always
+// lands in y_out.
+template <int T, int NT, bool STAGED>
+__global__ __launch_bounds__(NT) void k_chain(ChainArgs c) {
+    extern __shared__ __align__(16) float lds[];
+    unsigned gen = 0u;
+    const int N = c.N, L = c.L;
+    const size_t NK = (size_t)N * K;
+    for (int l = 0; l < L; ++l) {
+        const int R = (l == 0 || !c.compaction) ? c.rows : ld_acquire(&c.cnt[l]);
+        if (R == 0) break;
+        const bool out_is_y = ((L - 1 - l) & 1) == 0;
+        LayerArgs a;
+        a.yin = l == 0 ? c.y0 : (out_is_y ? c.act : c.y_out);
+        a.yout = out_is_y ? c.y_out : c.act;
+        a.ycopy = (c.ckpt && (l + 1) % c.ckpt_every == 0 && l + 1 < L)
+                      ? c.ckpt + (size_t)((l + 1) / c.ckpt_every - 1) * c.rows * N
+                      : nullptr;
+        a.yzero = (c.compaction && !out_is_y) ? c.y_out : nullptr;
+        a.idx = c.idx + l * NK;
+        a.w = c.w + l * NK;
+        a.b = c.b + (size_t)l * N;
+        a.list_in = (l == 0 || !c.compaction) ? nullptr : ((l & 1) ? c.list1 : c.list0);
+        a.list_out = c.compaction ? (((l + 1) & 1) ? c.list1 : c.list0) : nullptr;
+        a.cnt_in = nullptr;
+        a.cnt_out = &c.cnt[l + 1];
+        a.alive = c.alive;
+        a.row_base = 0;
+        a.nrows = R;
+        a.N = N;
+        a.layer = l;
+        a.clamp = c.clamp;
+        run_layer<T, NT, STAGED>(a, lds, blockIdx.x, gridDim.x, R);
+        if (!grid_barrier(c.bar, gen, c.err)) return;
+    }
+    // the nz list and the row profile are produced by a k_finalize launch after this kernel
+}
+
+// ---------------------------------------------------------------- small kernels
+__global__ void k_chain_init(int32_t* cnt, int32_t L, int32_t rows, int32_t compaction, unsigned* bar, int32_t nbar) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= L; i += gridDim.x * blockDim.x)
+        cnt[i] = (i == 0 || !compaction) ? rows : 0;
+    if (bar)
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nbar; i += gridDim.x * blockDim.x) bar[i] = 0u;
+}
+
+__global__ void k_fill_f32(float* p, int64_t n, float v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Parameter validation: bit 1 = id out of range, 2 = ids not strictly ascending,
+// 4 = non-finite weight, 8 = non-finite bias.
+__global__ void k_check_params(const int32_t* idx, const float* w, const float* b, int32_t N, int32_t L, int32_t* bad,
+                               float* /*unused*/) {
+    const int64_t neurons = (int64_t)N * L;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < neurons; n += (int64_t)gridDim.x * blockDim.x) {
+        int flags = 0;
+        int prev = -1;
+        for (int k = 0; k < K; ++k) {
+            const int v = idx[n * K + k];
+            if (v < 0 || v >= N) flags |= 1;
+            if (v <= prev) flags |= 2;
+            prev = v;
+            if (!isfinite(w[n * K + k])) flags |= 4;
+        }
+        if (!isfinite(b[n])) flags |= 8;
+        if (flags) atomicOr(bad, flags);
+    }
+}
+
+// flag_pos[0] |= 1 if any bias is > 0 or NaN (compaction would not be exact).
+__global__ void k_max_bias(const float* b, int64_t n, int32_t* flag_pos) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = b[i];
+        if (!(v <= 0.f)) atomicOr(flag_pos, 1);
+    }
+}
+
+// MSE: dy = scale * (y - t); per-block partial sums of (y - t)^2 in a fixed order.
+constexpr int MSE_NT = 256;
+__global__ __launch_bounds__(MSE_NT) void k_mse(const float* y, const float* t, int64_t n, float* dy, float* partial,
+                                                float scale) {
+    __shared__ float s[MSE_NT];
+    float acc = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * MSE_NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * MSE_NT) {
+        const float d = y[i] - t[i];
+        if (dy) dy[i] = scale * d;
+        acc = fmaf(d, d, acc);
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = MSE_NT / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && partial) partial[blockIdx.x] = s[0];
+}
+
+__global__ void k_mse_final(const float* partial, int32_t nparts, float* loss, float inv_n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < nparts; ++i) s += partial[i];
+        *loss = (float)(s * inv_n);
+    }
+}
+
+// ---------------------------------------------------------------- variant table
+#define SDNN_V(T, NT) {T, NT, 1, (const void*)&k_layer<T, NT, true>, (const void*)&k_chain<T, NT, true>}
+#define SDNN_VD(T, NT) {T, NT, 0, (const void*)&k_layer<T, NT, false>, (const void*)&k_chain<T, NT, false>}
+static const FwdVariant g_variants[] = {
+    SDNN_V(1, 256),  SDNN_V(1, 512),  SDNN_V(1, 1024),
+    SDNN_V(2, 256),  SDNN_V(2, 512),  SDNN_V(2, 1024),
+    SDNN_V(4, 256),  SDNN_V(4, 512),  SDNN_V(4, 1024),
+    SDNN_V(8, 256),  SDNN_V(8, 512),  SDNN_V(8, 1024),
+    SDNN_V(16, 256), SDNN_V(16, 512), SDNN_V(16, 1024),
+    SDNN_V(32, 256), SDNN_V(32, 512),
+    SDNN_VD(1, 256), SDNN_VD(1, 512), SDNN_VD(1, 1024),
+    SDNN_VD(2, 256), SDNN_VD(4, 256),
+};
+#undef SDNN_V
+#undef SDNN_VD
+
+int fwd_variant_count() { return (int)(sizeof(g_variants) / sizeof(g_variants[0])); }
+const FwdVariant& fwd_variant(int i) { return g_variants[i]; }
+
+}  // namespace sdnn

@@ -1,0 +1,124 @@
+// Internal declarations shared by the kernels and the host side of the library.
+// Not part of the public ABI (include/sdnn.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sdnn {
+
+constexpr int K = 32;                    // inputs per neuron (the only supported k)
+constexpr int LDS_BYTES = 160 * 1024;    // gfx950 LDS per workgroup
+constexpr int MAX_BATCHES = 256;
+constexpr int BAR_WORDS = 10 * 32;       // grid-barrier words (10 lines of 128 B)
+
+// Arguments of one forward layer over a set of rows.
+//  Row ids index the [*][N] buffers; row p of the work list is
+//    list_in ? list_in[p] : row_base + p,   p < (cnt_in ? *cnt_in : nrows).
+struct LayerArgs {
+    const float* yin;        // activations entering the layer
+    float* yout;             // activations leaving it (same row ids)
+    float* ycopy;            // optional second copy of the output rows (checkpoint), or null
+    float* yzero;            // rows found all-zero are also zeroed here (or null)
+    const int32_t* idx;      // [N][K] this layer
+    const float* w;          // [N][K]
+    const float* b;          // [N]
+    const int32_t* list_in;  // work list (null = identity)
+    int32_t* list_out;       // rows with a nonzero output are appended here (null = no compaction)
+    const int32_t* cnt_in;   // device row count of the work list (null = nrows)
+    int32_t* cnt_out;        // append counter for list_out
+    int32_t* alive;          // alive[row] = output row nonzero (or null)
+    int32_t row_base;
+    int32_t nrows;
+    int32_t N;
+    int32_t layer;
+    float clamp;
+};
+
+// Whole forward pass run by the persistent kernel (all layers, one launch).
+struct ChainArgs {
+    const float* y0;         // [rows][N] input
+    float* y_out;            // [rows][N] output, ping-pong buffer "X"
+    float* act;              // [rows][N] workspace ping-pong buffer
+    float* ckpt;             // checkpoints or null
+    const int32_t* idx;      // [L][N][K]
+    const float* w;          // [L][N][K]
+    const float* b;          // [L][N]
+    int32_t* list0;          // [rows]
+    int32_t* list1;          // [rows]
+    int32_t* cnt;            // [L+1]
+    int32_t* alive;          // [rows]
+    unsigned* bar;           // barrier words (see grid_barrier)
+    int32_t* err;            // device error word
+    int32_t rows;
+    int32_t N;
+    int32_t L;
+    int32_t ckpt_every;
+    int32_t compaction;
+    float clamp;
+};
+
+// Error codes written to the device error word.
+enum DeviceError : int32_t { DEV_OK = 0, DEV_BARRIER_TIMEOUT = 1 };
+
+// Kernel variant table (instantiated in sdnn_fwd.hip).
+struct FwdVariant {
+    int T;          // rows per tile
+    int NT;         // threads per workgroup
+    int staged;     // 1 = rows staged in LDS, 0 = direct gather from global memory
+    const void* layer_fn;    // __global__ void(LayerArgs)
+    const void* chain_fn;    // __global__ void(ChainArgs)  (cooperative)
+};
+int fwd_variant_count();
+const FwdVariant& fwd_variant(int i);
+inline size_t fwd_lds_bytes(const FwdVariant& v, int N) { return v.staged ? (size_t)v.T * N * sizeof(float) : 0; }
+
+// Small kernels (sdnn_fwd.hip).
+__global__ void k_chain_init(int32_t* cnt, int32_t L, int32_t rows, int32_t compaction, unsigned* bar, int32_t nbar);
+__global__ void k_finalize(const int32_t* alive, int32_t rows, int32_t* nz_rows, int32_t* n_nz, const int32_t* cnt,
+                           int32_t n_regions, int32_t L, int32_t* layer_rows);
+__global__ void k_fill_f32(float* p, int64_t n, float v);
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v);
+__global__ void k_check_params(const int32_t* idx, const float* w, const float* b, int32_t N, int32_t L,
+                               int32_t* bad, float* max_bias);
+__global__ void k_max_bias(const float* b, int64_t n, int32_t* flag_pos);
+__global__ void k_mse(const float* y, const float* t, int64_t n, float* dy, float* partial, float scale);
+__global__ void k_mse_final(const float* partial, int32_t nparts, float* loss, float inv_n);
+
+// Backward kernels (sdnn_bwd.hip).
+struct BwdDwArgs {
+    const float* y_in;       // [R][N] compact Y_l
+    const float* y_out;      // [R][N] compact Y_{l+1} (mask)
+    const float* dy;         // [R][N] compact dL/dY_{l+1}
+    const int32_t* idx;      // [N][K]
+    const int32_t* nrows;    // device R
+    float* pdw;              // [P][N][K] partials
+    float* pdb;              // [P][N]
+    int32_t N;
+    int32_t P;               // row groups
+    float clamp;
+};
+struct BwdDyArgs {
+    const float* y_out;      // [R][N] Y_{l+1}
+    const float* dy;         // [R][N] dL/dY_{l+1}
+    const int32_t* tr_ptr;   // [N+1]
+    const int32_t* tr_e;     // [N*K] edge positions j*K+k grouped by input neuron
+    const float* w;          // [N][K]
+    const int32_t* nrows;    // device R
+    const int32_t* rows_out; // optional: output row r goes to rows_out[r] (scatter), else r
+    float* dy_in;            // output dL/dY_l
+    int32_t N;
+    float clamp;
+};
+int bwd_T();
+int bwd_threads();
+const void* bwd_dw_fn();
+const void* bwd_dy_fn();
+__global__ void k_reduce_partials(const float* pdw, const float* pdb, int32_t P, int32_t N, float* dw, float* db);
+__global__ void k_gather_rows(const float* src, const int32_t* rows, const int32_t* n, int32_t N, float* dst);
+__global__ void k_tr_count(const int32_t* idx, int64_t nnz, int32_t* deg);
+__global__ void k_tr_scan(const int32_t* deg, int32_t N, int32_t* ptr);
+__global__ void k_tr_fill(const int32_t* idx, int64_t nnz, const int32_t* ptr, int32_t* cursor, int32_t* tr_e);
+__global__ void k_tr_sort(const int32_t* ptr, int32_t N, int32_t* tr_e);
+
+}  // namespace sdnn

@@ -198,10 +198,40 @@ def make_batches(cfg: NetConfig) -> np.ndarray:
     return np.concatenate([[0], np.cumsum(s)]).astype(np.int64)
 
 
+def make_layer_device(cfg: NetConfig, layer: int, device, k: Optional[int] = None):
+    """A layer with the same distributions, drawn by torch's device generator.
+
+    A second, faster stream (seeded with ``seed * 1000003 + layer``) for the deep
+    parts of large nets; it does not reproduce ``make_layer``'s values.
+    Returns (idx int32 [N][K], w fp32 [N][K], bias fp32 [N]) on ``device``.
+    """
+    import torch
+    N, K = cfg.n_neurons, cfg.k if k is None else k
+    g = torch.Generator(device=device)
+    g.manual_seed(cfg.seed * 1000003 + layer)
+    idx = torch.randint(0, N, (N, K), generator=g, device=device, dtype=torch.int64)
+    while True:
+        idx, _ = torch.sort(idx, dim=1)
+        dup = (idx[:, 1:] == idx[:, :-1]).any(dim=1)
+        nd = int(dup.sum())
+        if nd == 0:
+            break
+        idx[dup] = torch.randint(0, N, (nd, K), generator=g, device=device, dtype=torch.int64)
+    if cfg.weight == "const":
+        w = torch.full((N, K), 1.0 / 16.0, dtype=torch.float32, device=device)
+    elif cfg.weight == "uniform":
+        w = torch.rand((N, K), generator=g, device=device, dtype=torch.float32) * 0.06 + 0.03
+    else:
+        w = torch.randn((N, K), generator=g, device=device, dtype=torch.float32) * float(np.sqrt(2.0 / K))
+    b = torch.full((N,), float(np.float32(cfg.bias)), dtype=torch.float32, device=device)
+    return idx.to(torch.int32), w, b
+
+
 def tiny_config(n: int, layers: int, rows: int, seed: int, k: int = K_DEFAULT, **kw) -> NetConfig:
     """A small net for unit tests (any n >= k)."""
     return NetConfig(f"tiny{n}x{layers}", n, layers, rows, seed, k=k, **kw)
 
 
 __all__ = ["NetConfig", "CONFIGS", "layer_pattern", "layer_weights", "make_layer", "iter_layers", "make_net",
+           "make_layer_device",
            "teacher_weights", "make_inputs", "make_batches", "tiny_config", "K_DEFAULT"]

@@ -304,3 +304,44 @@ def test_mse_gradient(orc):
     eps = 1e-6
     y2 = y.copy(); y2[2, 3] += eps
     assert abs((orc.mse(y2, t)[0] - loss) / eps - g[2, 3]) < 1e-6
+
+
+# ---------------------------------------------------------------- forward error bound
+def fp32_chain(layers, y0, clamp, reverse=False):
+    """An independent fp32 evaluation (separate multiply and add, slot order or reversed)."""
+    y = np.asarray(y0, np.float32)
+    for idx, w, b in layers:
+        acc = np.zeros((y.shape[0], idx.shape[0]), np.float32)
+        ks = range(idx.shape[1] - 1, -1, -1) if reverse else range(idx.shape[1])
+        for k in ks:
+            acc = (acc + (w[:, k][None, :] * y[:, idx[:, k]]).astype(np.float32)).astype(np.float32)
+        z = (acc + b[None, :]).astype(np.float32)
+        y = np.minimum(np.float32(clamp), np.maximum(np.float32(0), z)).astype(np.float32)
+    return y
+
+
+@pytest.mark.parametrize("name,N,L,rows", [("S2", 1024, 12, 120), ("G5", 512, 10, 64), ("C5", 512, 4, 80)])
+def test_fp32_evaluations_stay_within_the_propagated_bound(orc, name, N, L, rows):
+    cfg = gen.CONFIGS[name].with_(n_neurons=N, n_layers=L, rows=rows, row_density=(name == "S2"))
+    layers = [l[1:] for l in gen.iter_layers(cfg)]
+    y0 = gen.make_inputs(cfg)
+    ref = orc.forward(layers, y0, cfg.clamp, bound=True)
+    for rev in (False, True):
+        y32 = fp32_chain(layers, y0, cfg.clamp, reverse=rev).astype(np.float64)
+        assert (np.abs(y32 - ref.y) <= ref.bound).all()
+    assert (ref.bound > 0).any()
+
+
+def test_fixed_relative_tolerance_is_unreachable_in_fp32_for_unsaturated_rows(orc):
+    """Each layer of the challenge nets has gain sum_k |w| = 32/16 = 2, so rounding
+    errors of any fp32 evaluation grow ~2^L on rows that never saturate: a fixed 1e-5
+    end-to-end relative check rejects a correct fp32 chain, the propagated bound does not."""
+    cfg = gen.CONFIGS["S2"].with_(n_neurons=1024, n_layers=12, rows=200)
+    layers = [l[1:] for l in gen.iter_layers(cfg)]
+    y0 = gen.make_inputs(cfg)
+    ref = orc.forward(layers, y0, cfg.clamp, bound=True)
+    y32 = fp32_chain(layers, y0, cfg.clamp).astype(np.float64)
+    scale = np.maximum(np.abs(ref.y), np.abs(ref.y).max(axis=1, keepdims=True))
+    assert (np.abs(y32 - ref.y) > 1e-5 * scale).any()
+    assert (np.abs(y32 - ref.y) <= np.maximum(1e-5 * scale, ref.bound)).all()
+    assert all(w.sum(axis=1).max() == 2.0 for _, w, _ in layers)

@@ -19,6 +19,7 @@ MUTANTS = {
     "dw_wrong_sign": ("dwj[k] += g * yi[ij[k]];", "dwj[k] -= g * yi[ij[k]];"),
     "dy_missing_weight": ("di[ij[k]] += g * (double)wj[k];", "di[ij[k]] += g;"),
     "db_missing": ("sb += g;", ""),
+    "bound_no_propagation": ("eo[j] = (1.0 + g) * prop + g * s;", "eo[j] = g * s;"),
 }
 
 
@@ -27,6 +28,7 @@ def _checks(orc):
     yield lambda: pins.test_forward_matches_dense_bruteforce(orc, 40, 8, 5, 17, 1.5, False)
     yield lambda: pins.test_backward_matches_dense_chain_rule(orc, 48, 8, 4, 9, 1.0)
     yield lambda: pins.test_first_layer_closed_form_on_binary_inputs(orc)
+    yield lambda: pins.test_fp32_evaluations_stay_within_the_propagated_bound(orc, "S2", 1024, 12, 120)
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
