@@ -1,0 +1,320 @@
+#!/usr/bin/env python3
+"""Benchmark of the layered sparse-DNN forward on one MI355X.
+
+Workload (the metric's configuration): 4096 neurons x 480 layers, 32 inputs per
+neuron (weights 1/16, bias -0.35, clip 32), 60000 Bernoulli(0.2) binary input
+rows, plain forward in fp32, drawn by the seeded generator in sdnn_inputs (seed 2).
+A step is one sdnn_forward over all 60000 rows and all 480 layers, with the
+network and the inputs resident in HBM.  The metric is edges/s =
+rows x nnz(W) / step time.
+
+Prints ONE JSON line.  Besides the required fields it carries:
+  roofline      the dominant kernel's algorithmic HBM bytes per launch / its
+                average duration, against MI355X's 8 TB/s
+  cpu_baseline  the FP64 oracle timed on this host on a bounded row sample
+  extras        sustained (S2), batched vs plain (C3), bwd/fwd ratio (G5),
+                engine comparison and a full-live layer, when --extras is on
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+K = 32
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--engine", default="auto", choices=["auto", "graph", "persistent", "eager"],
+                    help="auto: time graph and persistent in warm-up and keep the faster")
+    ap.add_argument("--extras", dest="extras", action="store_true", default=True)
+    ap.add_argument("--no-extras", dest="extras", action="store_false")
+    ap.add_argument("--cpu", dest="cpu", action="store_true", default=True)
+    ap.add_argument("--no-cpu", dest="cpu", action="store_false")
+    ap.add_argument("--cpu-rows", type=int, default=3000, help="row sample for the oracle baseline")
+    ap.add_argument("--tune", action="store_true", default=True)
+    ap.add_argument("--no-tune", dest="tune", action="store_false")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def forward_bytes(prof, N, L):
+    """Algorithmic HBM bytes of one forward from its row profile prof[0..L]:
+    per layer with R_l > 0 rows: 8NK (ids + weights) + 4N (bias) + 8 R_l N (read
+    and write the alive rows) + 4 (R_l + R_{l+1}) (work lists)."""
+    tot = 0
+    for l in range(L):
+        r, r1 = int(prof[l]), int(prof[l + 1])
+        if r > 0:
+            tot += 8 * N * K + 4 * N + 8 * r * N + 4 * (r + r1)
+    return tot
+
+
+def live_edges(prof, N, L):
+    return sum(int(prof[l]) for l in range(L)) * N * K
+
+
+def time_forward(torch, net, y0, out, steps, warmup, batch_off=None):
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        net.forward(y0, batch_off=batch_off, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        net.forward(y0, batch_off=batch_off, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the library has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2004_10908_amd as P
+    import sdnn_inputs as gen
+
+    if not os.path.exists(P.LIB_PATH):
+        from paper_2004_10908_amd import build as b
+        b.build()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    cfg = gen.CONFIGS["C2"]
+    N, L, B = cfg.n_neurons, cfg.n_layers, cfg.rows
+    nnz = cfg.nnz
+    t0 = time.time()
+    idx_h, w_h, b_h = gen.make_net(cfg)
+    y0_h = gen.make_inputs(cfg)
+    log(f"generated C2 in {time.time() - t0:.1f}s")
+    idx, w, b = (torch.from_numpy(a).to(dev) for a in (idx_h, w_h, b_h))
+    y0 = torch.from_numpy(y0_h).to(dev)
+    net = P.Net(idx, w, b, max_rows=B)
+    if args.tune:
+        plan = net.tune(8192)
+        log("tuned plan", plan)
+    out = {}
+    net.forward(y0, out=out, profile=True)
+
+    # engine choice (warm-up): graph vs persistent
+    engines = {}
+    cands = ["graph", "persistent"] if args.engine == "auto" else [args.engine]
+    for eng in cands:
+        net.set_exec(eng)
+        engines[eng] = time_forward(torch, net, y0, out, max(2, args.warmup), 1)
+    engine = min(engines, key=engines.get)
+    net.set_exec(engine)
+    log("warm-up engine times (ms)", engines, "->", engine)
+
+    # ---------------------------------------------------------------- timed region
+    ms = time_forward(torch, net, y0, out, args.steps, args.warmup)
+    prof = out["layer_rows"].cpu().numpy()
+    n_nz = int(out["n_nz"].item())
+    value = B * nnz / (ms / 1e3)
+    alg = forward_bytes(prof, N, L)
+    achieved = alg / (ms / 1e3) / 1e9
+    kernel = "k_chain (persistent forward, all layers)" if engine == "persistent" else "k_layer (480 graph nodes)"
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
+                "alg_bytes_per_launch": alg if engine == "persistent" else alg / L}
+    log(f"C2 {engine}: {ms:.3f} ms/step, {value:.3e} edges/s, profile head {prof[:5].tolist()}, nz {n_nz}")
+
+    extras = {"engines_ms": {k: round(v, 4) for k, v in engines.items()}, "plan": net.plan,
+              "c2_profile_head": prof[:6].tolist(), "c2_live_edges_per_s": live_edges(prof, N, L) / (ms / 1e3),
+              "c2_alg_bytes": alg}
+
+    # ---------------------------------------------------------------- extras
+    if args.extras:
+        try:
+            extras.update(bench_extras(args, torch, np, P, gen, dev, net, y0, idx, w, b))
+        except Exception as e:  # extras never hide the headline
+            extras["error"] = repr(e)
+            log("extras failed:", repr(e))
+    net.close()
+    del y0, idx, w, b, out
+    torch.cuda.empty_cache()
+
+    cpu = None
+    if args.cpu:
+        try:
+            cpu = cpu_baseline(args, np, gen, cfg, idx_h, w_h, b_h, y0_h)
+        except Exception as e:
+            log("cpu baseline failed:", repr(e))
+
+    line = {"metric": "edges/s (inputs x nnz(W) / s)", "value": value, "unit": "edges/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+            "config": {"workload": "C2 plain forward: 4096 neurons x 480 layers, k=32, w=1/16, b=-0.35, clip 32, "
+                                   "60000 Bernoulli(0.2) rows, seed 2", "global_batch": B, "seq_len": None,
+                       "parallelism": "single-gpu", "engine": engine},
+            "roofline": roofline, "cpu_baseline": cpu, "extras": extras}
+    print(json.dumps(line), flush=True)
+
+
+def full_live_layer(torch, net, y, reps=10):
+    """Time sdnn_layer on every row (no compaction): the steady-state kernel rate."""
+    yo = torch.empty_like(y)
+    stream = torch.cuda.current_stream()
+    net.layer(0, y, yo)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        net.layer(0, y, yo)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def device_net(torch, gen, cfg, dev, n_layers=None):
+    L = cfg.n_layers if n_layers is None else n_layers
+    idx = torch.empty((L, cfg.n_neurons, K), dtype=torch.int32, device=dev)
+    w = torch.empty((L, cfg.n_neurons, K), dtype=torch.float32, device=dev)
+    b = torch.empty((L, cfg.n_neurons), dtype=torch.float32, device=dev)
+    for l in range(L):
+        i_, w_, b_ = gen.make_layer_device(cfg, l, dev)
+        idx[l].copy_(i_)
+        w[l].copy_(w_)
+        b[l].copy_(b_)
+    return idx, w, b
+
+
+def device_inputs(torch, cfg, dev):
+    g = torch.Generator(device=dev)
+    g.manual_seed(cfg.seed * 7919 + 1)
+    if cfg.row_density:
+        p = torch.rand((cfg.rows, 1), generator=g, device=dev) * 0.4 + 0.1
+    else:
+        p = cfg.density
+    return (torch.rand((cfg.rows, cfg.n_neurons), generator=g, device=dev) < p).float()
+
+
+def bench_extras(args, torch, np, P, gen, dev, net_c2, y0_c2, idx2, w2, b2):
+    ex = {}
+    N = 4096
+    # full-live layer of C2's shape (every row alive): the gather kernel's steady-state rate
+    ms = full_live_layer(torch, net_c2, y0_c2)
+    byt = 8 * N * K + 4 * N + 8 * y0_c2.shape[0] * N
+    ex["full_live_layer"] = {"rows": y0_c2.shape[0], "ms": round(ms, 4), "alg_GBps": round(byt / ms / 1e6, 1),
+                             "frac": round(byt / ms / 1e6 / HBM_PEAK_GBS, 4),
+                             "edges_per_s": y0_c2.shape[0] * N * K / (ms / 1e3)}
+    log("full-live layer", ex["full_live_layer"])
+
+    # S2: sustained companion (rows stay alive), device-drawn net and inputs
+    cfg = gen.CONFIGS["S2"]
+    idx, w, b = device_net(torch, gen, cfg, dev)
+    y0 = device_inputs(torch, cfg, dev)
+    net = P.Net(idx, w, b, max_rows=cfg.rows)
+    net.plan_ = net.tune(8192)
+    o = {}
+    net.forward(y0, out=o, profile=True)
+    res = {}
+    for eng in ("graph", "persistent"):
+        net.set_exec(eng)
+        ms = time_forward(torch, net, y0, o, 3, 1)
+        prof = o["layer_rows"].cpu().numpy()
+        alg = forward_bytes(prof, N, cfg.n_layers)
+        res[eng] = {"ms": round(ms, 3), "edges_per_s": cfg.rows * cfg.nnz / (ms / 1e3),
+                    "live_edges_per_s": live_edges(prof, N, cfg.n_layers) / (ms / 1e3),
+                    "alg_GBps": round(alg / ms / 1e6, 1), "frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    res["alive_profile"] = [int(v) for v in prof[[0, 1, 2, 5, 10, 20, 100, 479, 480]]]
+    ex["S2"] = res
+    log("S2", res)
+    net.close()
+    del idx, w, b, y0, o
+    torch.cuda.empty_cache()
+
+    # C3: batched (one pass over all 20 uneven batches) vs plain (batches one after another)
+    for name in ("C3", "S3"):
+        cfg = gen.CONFIGS[name]
+        idx, w, b = device_net(torch, gen, cfg, dev)
+        y0 = device_inputs(torch, cfg, dev)
+        off = [int(v) for v in gen.make_batches(cfg)]
+        net = P.Net(idx, w, b, max_rows=cfg.rows)
+        o = {}
+        net.forward(y0, out=o, profile=True)
+        r = {}
+        for eng in ("graph", "graph_merged", "persistent"):
+            net.set_exec(eng)
+            ms = time_forward(torch, net, y0, o, 2 if name == "S3" else 3, 1, batch_off=off)
+            r[eng] = {"ms": round(ms, 3), "edges_per_s": cfg.rows * cfg.nnz / (ms / 1e3)}
+        prof = o["layer_rows"].cpu().numpy()
+        r["plain"] = "graph (batches one after another)"
+        r["batched_best"] = max(("graph_merged", "persistent"), key=lambda k: r[k]["edges_per_s"])
+        r["batched_over_plain"] = r[r["batched_best"]]["edges_per_s"] / r["graph"]["edges_per_s"]
+        r["alive_profile"] = [int(v) for v in prof[[0, 1, 2, 5, 10, 100, 479, 480]]]
+        ex[name] = r
+        log(name, r)
+        net.close()
+        del idx, w, b, y0, o
+        torch.cuda.empty_cache()
+
+    # G5: forward + backward (bwd/fwd ratio) on 4096 rows, checkpoints every 16 layers
+    cfg = gen.CONFIGS["G5"]
+    idx, w, b = device_net(torch, gen, cfg, dev)
+    y0 = device_inputs(torch, cfg, dev)
+    net = P.Net(idx, w, b, max_rows=cfg.rows, ckpt_every=16, flags=P.sdnn.SDNN_TRAINABLE)
+    net.set_exec("graph")
+    o = net.forward(y0, ckpt=True)
+    dy = torch.randn_like(o["y"]) * 1e-4
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        net.forward(y0, ckpt=True, out=o)
+        net.backward(y0, o["ckpt"], o["nz_rows"], o["n_nz"], dy)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    reps = 3
+    fwd_ms = bwd_ms = 0.0
+    for _ in range(reps):
+        e[0].record(stream)
+        net.forward(y0, ckpt=True, out=o)
+        e[1].record(stream)
+        net.backward(y0, o["ckpt"], o["nz_rows"], o["n_nz"], dy)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        fwd_ms += e[0].elapsed_time(e[1]) / reps
+        bwd_ms += e[1].elapsed_time(e[2]) / reps
+    ex["G5"] = {"fwd_ms": round(fwd_ms, 3), "bwd_ms": round(bwd_ms, 3), "bwd_over_fwd": round(bwd_ms / fwd_ms, 3),
+                "n_nz": int(o["n_nz"].item()), "fwd_edges_per_s": cfg.rows * cfg.nnz / (fwd_ms / 1e3)}
+    log("G5", ex["G5"])
+    net.close()
+    return ex
+
+
+def cpu_baseline(args, np, gen, cfg, idx_h, w_h, b_h, y0_h):
+    import oracle
+    oracle.build()
+    rows = min(args.cpu_rows, cfg.rows)
+    sample = y0_h[:rows]
+    layers = [(idx_h[l], w_h[l], b_h[l]) for l in range(cfg.n_layers)]
+    t0 = time.perf_counter()
+    oracle.forward(layers, sample, cfg.clamp)
+    dt = time.perf_counter() - t0
+    return {"value": rows * cfg.nnz / dt, "unit": "edges/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"first {rows} of the 60000 C2 rows through all 480 layers (FP64, {dt:.1f} s)",
+            "seconds": round(dt, 2)}
+
+
+if __name__ == "__main__":
+    main()

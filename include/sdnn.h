@@ -164,6 +164,19 @@ sdnn_status sdnn_backward(sdnn_net net, const float *y0, int64_t rows, const flo
                           void *stream);
 
 /*
+ * Backward pass of one layer over `rows` rows (needs SDNN_TRAINABLE), the same
+ * kernels sdnn_backward chains:
+ *   G = dy_out * [0 < y_out < c];  dbias[j] = sum_r G[r][j];
+ *   dw[j][s] = sum_r G[r][j] y_in[r][idx[j][s]];  dy_in[r][i] = sum_{(j,s): idx[j][s]=i} G[r][j] w[j][s].
+ *   y_in, y_out, dy_out dev fp32 [rows][N] (y_out = this layer's forward output);
+ *   dw dev fp32 [N][k], dbias dev fp32 [N] (this layer's slices; overwritten);
+ *   dy_in dev fp32 [rows][N] or NULL.  rows <= max_rows.
+ */
+sdnn_status sdnn_layer_backward(sdnn_net net, int32_t layer, const float *y_in, const float *y_out,
+                                const float *dy_out, int64_t rows, float *dw, float *dbias, float *dy_in,
+                                void *stream);
+
+/*
  * Mean-squared-error loss of y against t (n elements) and its gradient:
  *   dy (dev fp32 [n], may be NULL) = 2 (y - t) / n
  *   loss (dev fp32 [257], may be NULL): loss[0] = sum (y - t)^2 / n; loss[1..256]

@@ -175,6 +175,7 @@ class ForwardResult:
     ambiguous: List[int] = field(default_factory=list)   # tie-ambiguous outputs per layer (if asked)
     ys: Optional[List[np.ndarray]] = None  # Y_0..Y_L, each [B][N] double (if asked)
     bound: Optional[np.ndarray] = None    # [B][N] forward error bound of any fp32 evaluation (if asked)
+    bounds: Optional[List[np.ndarray]] = None  # E_0..E_L per layer (if keep and bound)
 
     @property
     def nz_rows(self) -> np.ndarray:
@@ -195,6 +196,7 @@ def forward(layers: Iterable[Tuple[np.ndarray, np.ndarray, np.ndarray]], y0: np.
     y = np.array(y0, dtype=np.float64, copy=True)
     B = y.shape[0]
     err = np.zeros_like(y) if bound else None
+    errs = [err.copy()] if (bound and keep) else None
     act = np.ones(B, bool) if not compact else (y != 0).any(axis=1)
     alive_after: List[int] = []
     amb: List[int] = []
@@ -218,8 +220,10 @@ def forward(layers: Iterable[Tuple[np.ndarray, np.ndarray, np.ndarray]], y0: np.
         act = alive_now if compact else np.ones(B, bool)
         if keep:
             ys.append(y.copy())
+            if errs is not None:
+                errs.append(err.copy())
     alive = (y != 0).any(axis=1)
-    return ForwardResult(y=y, alive=alive, alive_after=alive_after, ambiguous=amb, ys=ys, bound=err)
+    return ForwardResult(y=y, alive=alive, alive_after=alive_after, ambiguous=amb, ys=ys, bound=err, bounds=errs)
 
 
 def backward(layers: Sequence[Tuple[np.ndarray, np.ndarray, np.ndarray]], ys: Sequence[np.ndarray],

@@ -747,6 +747,58 @@ sdnn_status sdnn_backward(sdnn_net net, const float* y0, int64_t rows, const flo
     return SDNN_OK;
 }
 
+sdnn_status sdnn_layer_backward(sdnn_net net, int32_t layer, const float* y_in, const float* y_out,
+                                const float* dy_out, int64_t rows, float* dw, float* dbias, float* dy_in,
+                                void* stream) {
+    if (!net) return fail(SDNN_EINVAL, "net is NULL");
+    const sdnn_desc& d = net->d;
+    if (!trainable(d)) return fail(SDNN_EINVAL, "net was not created with SDNN_TRAINABLE");
+    if (layer < 0 || layer >= d.n_layers) return fail(SDNN_EINVAL, "layer %d out of range", layer);
+    if (rows < 0 || rows > d.max_rows) return fail(SDNN_EINVAL, "rows out of range");
+    if (!dw || !dbias) return fail(SDNN_EINVAL, "dw and dbias are required");
+    if (rows > 0 && (!y_in || !y_out || !dy_out)) return fail(SDNN_EINVAL, "y_in, y_out and dy_out are required");
+    hipStream_t s = (hipStream_t)stream;
+    const int N = d.n_neurons;
+    const size_t NK = (size_t)N * K;
+    int32_t* nrows = net->flag + 2;                      // device copy of `rows`
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, nrows, (int64_t)1, (int32_t)rows);
+    const size_t bsh = (size_t)bwd_T() * N * 4;
+    BwdDwArgs da{};
+    da.y_in = y_in;
+    da.y_out = y_out;
+    da.dy = dy_out;
+    da.idx = net->idx + layer * NK;
+    da.nrows = nrows;
+    da.pdw = net->pdw;
+    da.pdb = net->pdb;
+    da.N = N;
+    da.P = P_GROUPS;
+    da.clamp = d.clamp;
+    void* dargs[] = {&da};
+    HIPCHK(hipLaunchKernel(bwd_dw_fn(), dim3(P_GROUPS, (N + bwd_threads() - 1) / bwd_threads()), dim3(bwd_threads()),
+                           dargs, bsh, s));
+    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for((int64_t)NK + N)), dim3(256), 0, s, (const float*)net->pdw,
+                       (const float*)net->pdb, (int32_t)P_GROUPS, (int32_t)N, dw, dbias);
+    if (dy_in && rows > 0) {
+        BwdDyArgs ya{};
+        ya.y_out = y_out;
+        ya.dy = dy_out;
+        ya.tr_ptr = net->tr_ptr + (size_t)layer * (N + 1);
+        ya.tr_e = net->tr_e + (size_t)layer * NK;
+        ya.w = net->w + layer * NK;
+        ya.nrows = nrows;
+        ya.rows_out = nullptr;
+        ya.dy_in = dy_in;
+        ya.N = N;
+        ya.clamp = d.clamp;
+        void* yargs[] = {&ya};
+        const int g = std::max(1, std::min<int>(net->num_cu * 2, (int)((rows + bwd_T() - 1) / bwd_T())));
+        HIPCHK(hipLaunchKernel(bwd_dy_fn(), dim3(g), dim3(bwd_threads()), yargs, bsh, s));
+    }
+    HIPCHK(hipGetLastError());
+    return SDNN_OK;
+}
+
 sdnn_status sdnn_mse(const float* y, const float* t, int64_t n, float* dy, float* loss, void* stream) {
     if (n < 0) return fail(SDNN_EINVAL, "n < 0");
     if (n > 0 && (!y || !t)) return fail(SDNN_EINVAL, "y and t are required");

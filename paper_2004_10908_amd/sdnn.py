@@ -51,6 +51,7 @@ PROTOTYPES = [
     ("sdnn_forward", _I32, [_P, _P, _I64, _P, _I32, _P, _P, _P, _P, _P, _P]),
     ("sdnn_layer", _I32, [_P, _I32, _P, _I64, _P, _P]),
     ("sdnn_backward", _I32, [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
+    ("sdnn_layer_backward", _I32, [_P, _I32, _P, _P, _P, _I64, _P, _P, _P, _P]),
     ("sdnn_mse", _I32, [_P, _P, _I64, _P, _P, _P]),
     ("sdnn_check_device", _I32, [_P, _P]),
     ("sdnn_destroy", None, [_P]),
@@ -157,6 +158,11 @@ def sdnn_backward(h, y0, rows, ckpt, nz_rows, n_nz, dy_out, dw, dbias, dy0=None,
                              _ptr(dbias), _ptr(dy0), _stream(stream)), "sdnn_backward")
 
 
+def sdnn_layer_backward(h, layer, y_in, y_out, dy_out, rows, dw, dbias, dy_in=None, stream=None) -> None:
+    _chk(lib().sdnn_layer_backward(h, layer, _ptr(y_in), _ptr(y_out), _ptr(dy_out), rows, _ptr(dw), _ptr(dbias),
+                                   _ptr(dy_in), _stream(stream)), "sdnn_layer_backward")
+
+
 def sdnn_mse(y, t, n, dy=None, loss=None, stream=None) -> None:
     _chk(lib().sdnn_mse(_ptr(y), _ptr(t), n, _ptr(dy), _ptr(loss), _stream(stream)), "sdnn_mse")
 
@@ -240,6 +246,13 @@ class Net:
         dy0 = torch.empty_like(y0) if want_dy0 else None
         sdnn_backward(self.h, y0, y0.shape[0], ckpt, nz_rows, n_nz, dy_out, dw, db, dy0, stream)
         return dw, db, dy0
+
+    def layer_backward(self, layer, y_in, y_out, dy_out, want_dy_in=True, stream=None):
+        dw = torch.empty_like(self.w[layer])
+        db = torch.empty_like(self.bias[layer])
+        dy_in = torch.empty_like(y_in) if want_dy_in else None
+        sdnn_layer_backward(self.h, layer, y_in, y_out, dy_out, y_in.shape[0], dw, db, dy_in, stream)
+        return dw, db, dy_in
 
     def check_device(self, stream=None) -> None:
         sdnn_check_device(self.h, stream)

@@ -34,6 +34,10 @@ class SparseDNNFunction(torch.autograd.Function):
         return dy0, dw, db, None
 
 
-def sparse_dnn(y0: torch.Tensor, net: Net):
-    """Differentiable forward: returns (y_out, nz_rows, n_nz)."""
-    return SparseDNNFunction.apply(y0, net.w, net.bias, net)
+def sparse_dnn(y0: torch.Tensor, net: Net, w: torch.Tensor = None, bias: torch.Tensor = None):
+    """Differentiable forward: returns (y_out, nz_rows, n_nz).
+
+    ``w`` / ``bias`` are the parameter tensors gradients should reach (leaf tensors
+    sharing storage with the ones the net was created over); default: the net's own.
+    """
+    return SparseDNNFunction.apply(y0, net.w if w is None else w, net.bias if bias is None else bias, net)

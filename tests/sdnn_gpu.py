@@ -90,14 +90,45 @@ def check_end_to_end(y_gpu, nz_gpu, ref):
     assert not bad.any(), f"{int(bad.sum())} outputs outside tolerance; worst excess {(err - tol)[bad].max()}"
 
 
-def check_grad(g_gpu, g_ref, s_g, rows, what):
+def check_grad(g_gpu, g_ref, bound, what, normwise=True):
+    """|g - g_ref| <= max(1e-4 |g_ref|, bound) elementwise, and (optionally) the
+    normwise 1e-4 check, which only holds where the chain is well conditioned."""
     g = np.asarray(g_gpu, np.float64)
     d = g - g_ref
-    nref = np.linalg.norm(g_ref)
-    assert np.linalg.norm(d) <= 1e-4 * nref + 1e-30, f"{what}: normwise {np.linalg.norm(d)} vs {nref}"
-    tol = np.maximum(1e-4 * np.abs(g_ref), oracle.gamma(max(rows, 1)) * s_g)
+    if normwise:
+        nref = np.linalg.norm(g_ref)
+        assert np.linalg.norm(d) <= 1e-4 * nref + 1e-30, f"{what}: normwise {np.linalg.norm(d)} vs {nref}"
+    tol = np.maximum(1e-4 * np.abs(g_ref), bound)
     bad = np.abs(d) > tol
-    assert not bad.any(), f"{what}: {int(bad.sum())} elements outside tolerance, worst {np.abs(d)[bad].max()}"
+    assert not bad.any(), f"{what}: {int(bad.sum())} elements outside tolerance, worst excess {(np.abs(d) - tol)[bad].max()}"
+
+
+def backward_bounds(layers, ys, eys, dy_last, clamp, rows_groups=64):
+    """First-order error bounds of an fp32 backward pass (masks taken as the oracle's).
+
+    ys/eys: exact activations and their forward error bounds per layer; dy_last is
+    the (exact, shared) dL/dY_L.  Uses the oracle's layer backward on magnitudes:
+    for dW the rounded terms are (|G| + E_G)(|Y| + E_Y), for dY they are |w|(|G| + E_G).
+    Returns per-layer (dW ref, E_dW, db ref, E_db) and (dY_0 ref, E_dY0).
+    """
+    L = len(layers)
+    R = ys[0].shape[0]
+    gR = oracle.gamma(R + rows_groups)
+    D = np.asarray(dy_last, np.float64)
+    ED = np.zeros_like(D)
+    out = [None] * L
+    for l in range(L - 1, -1, -1):
+        idx, w, _ = layers[l]
+        aw = np.abs(w)
+        Y, EY, Yo = ys[l], eys[l], ys[l + 1]
+        dw, db, dyi = oracle.layer_backward(idx, w, clamp, Y, Yo, D)
+        dwA, dbA, dyA = oracle.layer_backward(idx, aw, clamp, np.abs(Y) + EY, Yo, np.abs(D) + ED)
+        dwB, dbB, dyB = oracle.layer_backward(idx, aw, clamp, np.abs(Y), Yo, np.abs(D))
+        gK = oracle.gamma(int(np.bincount(idx.ravel(), minlength=idx.shape[0]).max()) + 1)
+        out[l] = (dw, (dwA - dwB) + gR * dwA, db, (dbA - dbB) + gR * dbA)
+        ED = (dyA - dyB) + gK * dyA
+        D = dyi
+    return out, D, ED
 
 
 def run_forward(net, y0, batch_off=None, mode="auto", ckpt=False):
