@@ -83,7 +83,8 @@ typedef struct {
     int32_t rows_per_tile;   /* T: activation rows staged per workgroup tile */
     int32_t threads;         /* workgroup size */
     int32_t grid;            /* workgroups per layer launch (grid-stride over tiles) */
-    int32_t variant;         /* 0 = LDS-staged rows, 1 = direct gather (rows too wide for LDS) */
+    int32_t variant;         /* 2 = scheduled resident-weight kernel, 0 = LDS-staged rows,
+                                1 = direct gather (rows too wide for LDS) */
     float tuned_us;          /* measured time per full-live layer of the tuning shape (0 if untuned) */
 } sdnn_plan;
 
@@ -183,6 +184,24 @@ sdnn_status sdnn_layer_backward(sdnn_net net, int32_t layer, const float *y_in, 
  *   are scratch for per-block partial sums.  The loss is reduced in a fixed order.
  */
 sdnn_status sdnn_mse(const float *y, const float *t, int64_t n, float *dy, float *loss, void *stream);
+
+/*
+ * Host-side slot schedule of the resident-weight forward kernel, as sdnn_create
+ * builds it (no GPU involved).  For each block of 64 neurons the neurons are
+ * spread over the four 16-lane LDS service units of a wave and each lane's 32
+ * slots are ordered so that, at every step, the 16 lanes of a unit read 16
+ * distinct LDS bank groups (input id mod 16); lanes are padded to the block's
+ * step count with weight-0 steps.
+ *   idx          host int32 [L][N][k] (ids in [0, N))
+ *   ent          host uint32 [L][npad][dmax]: (id << 5) | slot, or a pad step
+ *                (bit 31 set, id = a free bank group); npad = 64 * ceil(N / 64)
+ *   lane_neuron  host int32 [L][npad]: neuron computed by each lane slot, -1 if none
+ *   steps        host int32 [L][ceil(N / 64)]: steps of each block
+ * Returns the largest block step count (> dmax: the schedule does not fit and the
+ * entries past dmax were dropped), or SDNN_EINVAL / SDNN_EUNSUPPORTED.
+ */
+int32_t sdnn_schedule_host(const int32_t *idx, int32_t n_neurons, int32_t n_layers, int32_t dmax, uint32_t *ent,
+                           int32_t *lane_neuron, int32_t *steps);
 
 /* Synchronize `stream` and report whether a kernel of this net raised its error word. */
 sdnn_status sdnn_check_device(sdnn_net net, void *stream);

@@ -57,11 +57,21 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Layout {
     size_t act = 0, list0 = 0, list1 = 0, alive = 0, cnt = 0, bar = 0, err = 0, flag = 0;
+    size_t ent = 0, lane_neuron = 0, wave_steps = 0, tile_bits = 0, tile_cnt = 0;
+    bool sched = false;
     size_t tr_ptr = 0, tr_e = 0, seg = 0, gbuf0 = 0, gbuf1 = 0, pdw = 0, pdb = 0;
     size_t total = 0;
 };
 
 bool trainable(const sdnn_desc& d) { return (d.flags & SDNN_TRAINABLE) != 0; }
+
+// The scheduled resident-weight kernel needs two 4-row tiles in LDS, ids in
+// groups of 16, and at most 4 parts of 1024 neurons (grid of 256 = 8 XCDs x 32).
+bool sched_possible(const sdnn_desc& d) {
+    const int nblk = (d.n_neurons + 63) / 64;
+    const int G = (nblk + 15) / 16;
+    return d.n_neurons % 16 == 0 && (size_t)2 * SCHED_T * d.n_neurons * 4 <= LDS_BUDGET && (G == 1 || G == 2 || G == 4);
+}
 
 Layout make_layout(const sdnn_desc& d) {
     Layout y;
@@ -77,6 +87,15 @@ Layout make_layout(const sdnn_desc& d) {
     y.list1 = take(R * 4);
     y.alive = take(R * 4);
     y.cnt = take((size_t)MAX_BATCHES * (L + 1) * 4);
+    y.sched = sched_possible(d);
+    if (y.sched) {
+        const size_t nblk = (N + 63) / 64, npad = nblk * 64;
+        y.ent = take(L * npad * SCHED_DMAX * 4);
+        y.lane_neuron = take(L * npad * 4);
+        y.wave_steps = take(L * nblk * 4);
+        y.tile_bits = take(((R + SCHED_T - 1) / SCHED_T) * 4);
+        y.tile_cnt = take(((R + SCHED_T - 1) / SCHED_T) * 4);
+    }
     y.bar = take(NBAR * 4);
     y.err = take(64);
     y.flag = take(64);
@@ -162,6 +181,10 @@ struct sdnn_net_s {
     int32_t *tr_ptr = nullptr, *tr_e = nullptr;
     float *seg = nullptr, *gbuf0 = nullptr, *gbuf1 = nullptr, *pdw = nullptr, *pdb = nullptr;
     bool compaction = true;
+    bool sched = false;                 // scheduled kernel available (schedule built)
+    uint32_t* ent = nullptr;
+    int32_t *lane_neuron = nullptr, *wave_steps = nullptr, *tile_bits = nullptr, *tile_cnt = nullptr;
+    int parts = 1, nblk = 0;
     int exec = SDNN_EXEC_AUTO;
     int variant = 0;
     int grid = 0;
@@ -178,9 +201,30 @@ namespace {
 
 const FwdVariant& var(const sdnn_net_s* n) { return fwd_variant(n->variant); }
 
-bool variant_fits(const FwdVariant& v, int N) {
+bool variant_fits(const sdnn_net_s* n, const FwdVariant& v) {
+    if (v.staged == 2) return n->sched;
     if (!v.staged) return true;
-    return (size_t)v.T * N * 4 <= LDS_BUDGET;
+    return (size_t)v.T * n->d.n_neurons * 4 <= LDS_BUDGET;
+}
+
+// Schedule fields of layer l (the scheduled kernel reads them; others ignore them).
+void fill_sched(const sdnn_net_s* n, LayerArgs& a, int l) {
+    if (!n->sched) return;
+    const size_t npad = (size_t)n->nblk * 64;
+    a.ent = n->ent + (size_t)l * npad * SCHED_DMAX;
+    a.lane_neuron = n->lane_neuron + (size_t)l * npad;
+    a.wave_steps = n->wave_steps + (size_t)l * n->nblk;
+    a.tile_bits = n->tile_bits;
+    a.tile_cnt = n->tile_cnt;
+    a.parts = n->parts;
+    a.nblk = n->nblk;
+}
+
+// Workgroups of a layer launch: grid-stride kernels shrink to the tile count; the
+// scheduled kernel keeps its full (XCD x part) grid and idle workgroups exit.
+int launch_grid(const sdnn_net_s* n, const FwdVariant& v, int64_t rows) {
+    if (v.staged == 2) return n->grid;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(n->grid, (rows + v.T - 1) / v.T));
 }
 
 sdnn_status prepare_variant(sdnn_net_s* n, int vi, int* grid, int* chain_grid) {
@@ -197,12 +241,17 @@ sdnn_status prepare_variant(sdnn_net_s* n, int vi, int* grid, int* chain_grid) {
     return SDNN_OK;
 }
 
-// Default tile plan: the widest power-of-two row tile that fits the LDS budget.
-int default_variant(int N) {
+// Default tile plan: the scheduled kernel when its schedule exists, else the
+// widest power-of-two row tile that fits the LDS budget.
+int default_variant(const sdnn_net_s* n) {
+    const int N = n->d.n_neurons;
+    if (n->sched)
+        for (int i = 0; i < fwd_variant_count(); ++i)
+            if (fwd_variant(i).staged == 2) return i;
     int best = -1, bestT = 0;
     for (int i = 0; i < fwd_variant_count(); ++i) {
         const FwdVariant& v = fwd_variant(i);
-        if (!v.staged || !variant_fits(v, N) || v.T > 16) continue;
+        if (v.staged != 1 || (size_t)v.T * N * 4 > LDS_BUDGET || v.T > 16) continue;
         const int want_nt = v.T >= 16 ? 512 : 1024;
         if (v.NT != want_nt) continue;
         if (v.T > bestT) { bestT = v.T; best = i; }
@@ -279,6 +328,7 @@ LayerArgs layer_args_chain(const sdnn_net_s* n, int l, const float* y0, float* y
     a.N = N;
     a.layer = l;
     a.clamp = n->d.clamp;
+    fill_sched(n, a, l);
     return a;
 }
 
@@ -299,9 +349,7 @@ Plan plan_chain(const sdnn_net_s* n, const float* y0, int64_t rows, const int64_
                        (int32_t)(n->compaction ? 1 : 0), (unsigned*)nullptr, (int32_t)0));
         for (int l = 0; l < L; ++l) {
             LayerArgs a = layer_args_chain(n, l, y0, y_out, ckpt, rows, r0, nbr, cr);
-            const int ntiles = (nbr + v.T - 1) / v.T;
-            const int g = std::max(1, std::min(n->grid, ntiles));
-            p.push_back(mk(v.layer_fn, dim3(g), dim3(v.NT), sh, a));
+            p.push_back(mk(v.layer_fn, dim3(launch_grid(n, v, nbr)), dim3(v.NT), sh, a));
         }
         ++region;
     }
@@ -345,6 +393,15 @@ Plan plan_persistent(const sdnn_net_s* n, const float* y0, int64_t rows, float* 
     c.ckpt_every = n->d.ckpt_every > 0 ? n->d.ckpt_every : L + 1;
     c.compaction = n->compaction ? 1 : 0;
     c.clamp = n->d.clamp;
+    if (n->sched) {
+        c.ent = n->ent;
+        c.lane_neuron = n->lane_neuron;
+        c.wave_steps = n->wave_steps;
+        c.tile_bits = n->tile_bits;
+        c.tile_cnt = n->tile_cnt;
+        c.parts = n->parts;
+        c.nblk = n->nblk;
+    }
     auto ch = mk(v.chain_fn, dim3(n->chain_grid), dim3(v.NT), sh, c);
     ch->cooperative = true;
     p.push_back(std::move(ch));
@@ -476,7 +533,39 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
         HIPCHK(hipFuncSetAttribute(bwd_dy_fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bsh));
     }
     (void)nnz;
-    n->variant = default_variant(N);
+    if (lay.sched) {
+        // slot schedule of every layer, built on the host from a copy of the ids
+        n->nblk = (N + 63) / 64;
+        n->parts = (n->nblk + 15) / 16;
+        const size_t npad = (size_t)n->nblk * 64;
+        n->ent = (uint32_t*)(n->ws + lay.ent);
+        n->lane_neuron = (int32_t*)(n->ws + lay.lane_neuron);
+        n->wave_steps = (int32_t*)(n->ws + lay.wave_steps);
+        n->tile_bits = (int32_t*)(n->ws + lay.tile_bits);
+        n->tile_cnt = (int32_t*)(n->ws + lay.tile_cnt);
+        std::vector<int32_t> hidx((size_t)L * N * K);
+        HIPCHK(hipMemcpyAsync(hidx.data(), idx, hidx.size() * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        bool ids_ok = true;
+        for (size_t i = 0; i < hidx.size() && ids_ok; ++i) ids_ok = hidx[i] >= 0 && hidx[i] < N;
+        if (ids_ok) {
+            std::vector<uint32_t> hent((size_t)L * npad * SCHED_DMAX);
+            std::vector<int32_t> hln((size_t)L * npad), hws((size_t)L * n->nblk);
+            const int worst = build_schedule(hidx.data(), N, L, SCHED_DMAX, hent.data(), hln.data(), hws.data());
+            if (worst <= SCHED_DMAX) {
+                HIPCHK(hipMemcpyAsync(n->ent, hent.data(), hent.size() * 4, hipMemcpyHostToDevice, s));
+                HIPCHK(hipMemcpyAsync(n->lane_neuron, hln.data(), hln.size() * 4, hipMemcpyHostToDevice, s));
+                HIPCHK(hipMemcpyAsync(n->wave_steps, hws.data(), hws.size() * 4, hipMemcpyHostToDevice, s));
+                const int64_t nt = (std::max<int64_t>(desc->max_rows, 1) + SCHED_T - 1) / SCHED_T;
+                hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nt)), dim3(256), 0, s, n->tile_bits, nt, 0);
+                hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nt)), dim3(256), 0, s, n->tile_cnt, nt, 0);
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipStreamSynchronize(s));
+                n->sched = true;
+            }
+        }
+    }
+    n->variant = default_variant(n.get());
     TRY(prepare_variant(n.get(), n->variant, &n->grid, &n->chain_grid));
     HIPCHK(hipStreamSynchronize(s));
     sdnn_net net = n.release();
@@ -504,7 +593,7 @@ sdnn_status sdnn_get_plan(sdnn_net net, sdnn_plan* plan) {
     plan->rows_per_tile = v.T;
     plan->threads = v.NT;
     plan->grid = net->grid;
-    plan->variant = v.staged ? 0 : 1;
+    plan->variant = v.staged == 2 ? 2 : (v.staged ? 0 : 1);
     plan->tuned_us = net->tuned_us;
     return SDNN_OK;
 }
@@ -524,9 +613,12 @@ sdnn_status sdnn_tune(sdnn_net net, int64_t rows, void* stream) {
     HIPCHK(hipEventCreate(&e1));
     float best = 1e30f;
     int best_v = net->variant, best_g = net->grid, best_cg = net->chain_grid;
+    // Variants of one family share the per-output arithmetic order (the scheduled
+    // kernel sums slots in schedule order), so tuning never changes results.
+    const bool fam_sched = var(net).staged == 2;
     for (int vi = 0; vi < fwd_variant_count(); ++vi) {
         const FwdVariant& v = fwd_variant(vi);
-        if (!variant_fits(v, N)) continue;
+        if (!variant_fits(net, v) || (v.staged == 2) != fam_sched) continue;
         int g = 0, cg = 0;
         if (prepare_variant(net, vi, &g, &cg) != SDNN_OK) continue;
         LayerArgs a{};
@@ -538,7 +630,8 @@ sdnn_status sdnn_tune(sdnn_net net, int64_t rows, void* stream) {
         a.nrows = (int32_t)rt;
         a.N = N;
         a.clamp = net->d.clamp;
-        const int gg = std::max(1, std::min<int>(g, (int)((rt + v.T - 1) / v.T)));
+        fill_sched(net, a, 0);
+        const int gg = v.staged == 2 ? g : std::max(1, std::min<int>(g, (int)((rt + v.T - 1) / v.T)));
         void* args[] = {&a};
         const size_t sh = fwd_lds_bytes(v, N);
         HIPCHK(hipLaunchKernel(v.layer_fn, dim3(gg), dim3(v.NT), args, sh, s));
@@ -649,7 +742,8 @@ sdnn_status sdnn_layer(sdnn_net net, int32_t layer, const float* y_in, int64_t r
     a.N = d.n_neurons;
     a.layer = layer;
     a.clamp = d.clamp;
-    const int g = std::max(1, std::min<int>(net->grid, (int)((rows + v.T - 1) / v.T)));
+    fill_sched(net, a, layer);
+    const int g = launch_grid(net, v, rows);
     void* args[] = {&a};
     HIPCHK(hipLaunchKernel(v.layer_fn, dim3(g), dim3(v.NT), args, fwd_lds_bytes(v, d.n_neurons), (hipStream_t)stream));
     return SDNN_OK;
@@ -686,7 +780,7 @@ sdnn_status sdnn_backward(sdnn_net net, const float* y0, int64_t rows, const flo
     hipLaunchKernelGGL(k_gather_rows, dim3(gather_grid), dim3(256), 0, s, dy_out, nz_rows, n_nz, N, D);
     const FwdVariant& v = var(net);
     const size_t fsh = fwd_lds_bytes(v, N);
-    const int fgrid = std::max(1, std::min<int>(net->grid, (int)((rows + v.T - 1) / v.T)));
+    const int fgrid = launch_grid(net, v, rows);
     const size_t bsh = (size_t)bwd_T() * N * 4;
     const int dy_grid = std::max(1, std::min<int>(net->num_cu * 2, (int)((rows + bwd_T() - 1) / bwd_T())));
     for (int sg = nseg - 1; sg >= 0; --sg) {
@@ -704,6 +798,7 @@ sdnn_status sdnn_backward(sdnn_net net, const float* y0, int64_t rows, const flo
             a.N = N;
             a.layer = l;
             a.clamp = d.clamp;
+            fill_sched(net, a, l);
             void* args[] = {&a};
             HIPCHK(hipLaunchKernel(v.layer_fn, dim3(fgrid), dim3(v.NT), args, fsh, s));
         }
@@ -815,6 +910,15 @@ sdnn_status sdnn_mse(const float* y, const float* t, int64_t n, float* dy, float
     }
     HIPCHK(hipGetLastError());
     return SDNN_OK;
+}
+
+int32_t sdnn_schedule_host(const int32_t* idx, int32_t n_neurons, int32_t n_layers, int32_t dmax, uint32_t* ent,
+                           int32_t* lane_neuron, int32_t* steps) {
+    if (!idx || !ent || !lane_neuron || !steps || n_neurons < K || n_layers < 1 || dmax < K)
+        return fail(SDNN_EINVAL, "bad arguments");
+    for (size_t i = 0; i < (size_t)n_neurons * n_layers * K; ++i)
+        if (idx[i] < 0 || idx[i] >= n_neurons) return fail(SDNN_EINVAL, "id out of range");
+    return build_schedule(idx, n_neurons, n_layers, dmax, ent, lane_neuron, steps);
 }
 
 sdnn_status sdnn_check_device(sdnn_net net, void* stream) {

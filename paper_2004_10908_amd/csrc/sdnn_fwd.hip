@@ -310,6 +310,211 @@ __global__ __launch_bounds__(NT) void k_chain(ChainArgs c) {
     // the nz list and the row profile are produced by a k_finalize launch after this kernel
 }
 
+// ---------------------------------------------------------------- scheduled kernel
+// Resident-weight variant for rows that fit LDS twice at 4 rows per tile
+// (N <= 4096).  A workgroup of 1024 lanes owns 1024 neurons ("part") for the
+// whole layer: each lane keeps its neuron's slot schedule (LDS byte offsets) and
+// weights in registers, so the weights are read once per layer per workgroup
+// instead of once per tile.  Tiles of 4 rows are staged into one of two LDS
+// buffers with asynchronous global->LDS loads while the other buffer is being
+// consumed.  The slot order comes from the create-time scheduler, so every
+// 16-byte LDS read of a lane unit hits 16 distinct bank groups.  With G parts
+// per layer (G = ceil(N / 1024)), the G workgroups that share a tile combine
+// their row bits with device atomics; the last one to finish the tile appends
+// the alive rows, writes the alive flags and zeroes dead rows where needed.
+// Workgroup b serves part (b/8) % G of tile stream (b/(8G))*8 + b%8, so the parts
+// of a tile run on the same XCD (blockIdx % 8) and share its L2.
+template <int NT, int DMAX>
+__device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __restrict__ lds, int R) {
+    constexpr int T = SCHED_T;
+    __shared__ unsigned s_bits[2];
+    __shared__ unsigned s_final;
+    __shared__ int s_last;
+    const int N = a.N;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int G = a.parts;
+    const int b = blockIdx.x;
+    const int x = b & 7, kk = b >> 3;
+    const int p = kk % G;
+    const int q = (kk / G) * 8 + x;
+    const int S = (int)gridDim.x / G;
+    const int ntiles = (R + T - 1) / T;
+    if (q >= ntiles) return;                         // uniform over the workgroup
+    const int blk = p * (NT / 64) + wave;
+    const bool have = blk < a.nblk;
+    const int slot = blk * 64 + lane;
+    const int j = have ? a.lane_neuron[slot] : -1;
+    const int D = have ? __builtin_amdgcn_readfirstlane(a.wave_steps[blk]) : 0;
+    uint32_t off[DMAX];
+    float wv[DMAX];
+#pragma unroll
+    for (int st = 0; st < DMAX; ++st) {
+        const uint32_t e = (have && st < D) ? a.ent[(size_t)slot * DMAX + st] : (0x80000000u | 31u);
+        off[st] = ((e >> 5) & 0x03ffffffu) * (T * 4);
+        wv[st] = ((e & 0x80000000u) || j < 0) ? 0.f : a.w[(size_t)j * K + (e & 31u)];
+    }
+    const float bj = j >= 0 ? a.b[j] : 0.f;
+    const int nchunks = (T * N) / 64;                // 64 floats (16 ids x 4 rows) per chunk
+    auto row_of = [&](int tile, int t) {
+        const int pos = tile * T + t;
+        const int pp = pos < R ? pos : tile * T;     // padding rows repeat the tile's first row
+        return a.list_in ? a.list_in[pp] : a.row_base + pp;
+    };
+    auto stage = [&](int tile, int buf) {
+        const float* src = a.yin + (size_t)row_of(tile, lane & 3) * N + (lane >> 2);
+        float* dst = lds + (size_t)buf * T * N;
+        for (int c = wave; c < nchunks; c += NT / 64)
+            __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(src + 16 * c),
+                                             (void __attribute__((address_space(3)))*)(dst + 64 * c), 4, 0, 0);
+    };
+    if (tid == 0) { s_bits[0] = 0u; s_bits[1] = 0u; }
+    int it = 0;
+    if (q < ntiles) stage(q, 0);
+    for (int tile = q; tile < ntiles; tile += S, ++it) {
+        const int buf = it & 1;
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tile + S < ntiles) stage(tile + S, buf ^ 1);
+        if (tid == 0) s_bits[buf ^ 1] = 0u;
+        int rr[T];
+        bool vr[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            vr[t] = tile * T + t < R;
+            rr[t] = row_of(tile, t);
+        }
+        const char* L4 = reinterpret_cast<const char*>(lds + (size_t)buf * T * N);
+        float acc[T] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int st = 0; st < DMAX; ++st) {
+            if (st < D) {
+                const float4 v = *reinterpret_cast<const float4*>(L4 + off[st]);
+                acc[0] = fmaf(wv[st], v.x, acc[0]);
+                acc[1] = fmaf(wv[st], v.y, acc[1]);
+                acc[2] = fmaf(wv[st], v.z, acc[2]);
+                acc[3] = fmaf(wv[st], v.w, acc[3]);
+            }
+        }
+        unsigned bits = 0u;
+        if (j >= 0) {
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const float y = fminf(fmaxf(acc[t] + bj, 0.f), a.clamp);
+                if (vr[t]) {
+                    const size_t o = (size_t)rr[t] * N + j;
+                    a.yout[o] = y;
+                    if (a.ycopy) a.ycopy[o] = y;
+                    bits |= (y != 0.f ? 1u : 0u) << t;
+                }
+            }
+        }
+        if (!a.list_out && !a.alive) continue;      // recompute / single layer: no liveness
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o);
+        if (lane == 0 && bits) atomicOr(&s_bits[buf], bits);
+        __syncthreads();
+        if (tid == 0) {
+            unsigned all = s_bits[buf];
+            int last = 1;
+            if (G > 1) {
+                atomicOr(&a.tile_bits[tile], (int)all);
+                __threadfence();
+                last = atomicAdd(&a.tile_cnt[tile], 1) == G - 1;
+                if (last) {
+                    __threadfence();
+                    all = (unsigned)atomicOr(&a.tile_bits[tile], 0);
+                    atomicExch(&a.tile_bits[tile], 0);
+                    atomicExch(&a.tile_cnt[tile], 0);
+                }
+            }
+            if (last && a.list_out) {
+                int n = 0;
+#pragma unroll
+                for (int t = 0; t < T; ++t) n += (vr[t] && ((all >> t) & 1u)) ? 1 : 0;
+                if (n) {
+                    int base = atomicAdd(a.cnt_out, n);
+#pragma unroll
+                    for (int t = 0; t < T; ++t)
+                        if (vr[t] && ((all >> t) & 1u)) a.list_out[base++] = rr[t];
+                }
+            }
+            s_final = all;
+            s_last = last;
+        }
+        __syncthreads();
+        if (s_last) {
+            const unsigned all = s_final;
+            if (a.alive && tid < T && vr[tid < T ? tid : 0]) {
+#pragma unroll
+                for (int t = 0; t < T; ++t)
+                    if (t == tid) a.alive[rr[t]] = (int32_t)((all >> t) & 1u);
+            }
+            if (a.yzero) {
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    if (vr[t] && !((all >> t) & 1u)) {
+                        float* z = a.yzero + (size_t)rr[t] * N;
+                        for (int i = tid; i < N; i += NT) z[i] = 0.f;
+                    }
+                }
+            }
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+}
+
+template <int NT, int DMAX>
+__global__ __launch_bounds__(NT) void k_layer_sched(LayerArgs a) {
+    extern __shared__ __align__(16) float lds[];
+    const int R = a.cnt_in ? *a.cnt_in : a.nrows;
+    run_layer_sched<NT, DMAX>(a, lds, R);
+}
+
+template <int NT, int DMAX>
+__global__ __launch_bounds__(NT) void k_chain_sched(ChainArgs c) {
+    extern __shared__ __align__(16) float lds[];
+    unsigned gen = 0u;
+    const int N = c.N, L = c.L;
+    const size_t NK = (size_t)N * K;
+    const size_t npad = (size_t)c.nblk * 64;
+    for (int l = 0; l < L; ++l) {
+        const int R = (l == 0 || !c.compaction) ? c.rows : ld_acquire(&c.cnt[l]);
+        if (R == 0) break;
+        const bool out_is_y = ((L - 1 - l) & 1) == 0;
+        LayerArgs a;
+        a.yin = l == 0 ? c.y0 : (out_is_y ? c.act : c.y_out);
+        a.yout = out_is_y ? c.y_out : c.act;
+        a.ycopy = (c.ckpt && (l + 1) % c.ckpt_every == 0 && l + 1 < L)
+                      ? c.ckpt + (size_t)((l + 1) / c.ckpt_every - 1) * c.rows * N
+                      : nullptr;
+        a.yzero = (c.compaction && !out_is_y) ? c.y_out : nullptr;
+        a.idx = c.idx + l * NK;
+        a.w = c.w + l * NK;
+        a.b = c.b + (size_t)l * N;
+        a.list_in = (l == 0 || !c.compaction) ? nullptr : ((l & 1) ? c.list1 : c.list0);
+        a.list_out = c.compaction ? (((l + 1) & 1) ? c.list1 : c.list0) : nullptr;
+        a.cnt_in = nullptr;
+        a.cnt_out = &c.cnt[l + 1];
+        a.alive = c.alive;
+        a.row_base = 0;
+        a.nrows = R;
+        a.N = N;
+        a.layer = l;
+        a.clamp = c.clamp;
+        a.ent = c.ent + (size_t)l * npad * DMAX;
+        a.lane_neuron = c.lane_neuron + (size_t)l * npad;
+        a.wave_steps = c.wave_steps + (size_t)l * c.nblk;
+        a.tile_bits = c.tile_bits;
+        a.tile_cnt = c.tile_cnt;
+        a.parts = c.parts;
+        a.nblk = c.nblk;
+        run_layer_sched<NT, DMAX>(a, lds, R);
+        if (!grid_barrier(c.bar, gen, c.err)) return;
+    }
+}
+
 // ---------------------------------------------------------------- small kernels
 __global__ void k_chain_init(int32_t* cnt, int32_t L, int32_t rows, int32_t compaction, unsigned* bar, int32_t nbar) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= L; i += gridDim.x * blockDim.x)
@@ -396,6 +601,8 @@ static const FwdVariant g_variants[] = {
     SDNN_V(32, 256), SDNN_V(32, 512),
     SDNN_VD(1, 256), SDNN_VD(1, 512), SDNN_VD(1, 1024),
     SDNN_VD(2, 256), SDNN_VD(4, 256),
+    {SCHED_T, SCHED_NT, 2, (const void*)&k_layer_sched<SCHED_NT, SCHED_DMAX>,
+     (const void*)&k_chain_sched<SCHED_NT, SCHED_DMAX>},
 };
 #undef SDNN_V
 #undef SDNN_VD

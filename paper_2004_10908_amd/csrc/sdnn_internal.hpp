@@ -33,7 +33,19 @@ struct LayerArgs {
     int32_t N;
     int32_t layer;
     float clamp;
+    // scheduled (resident-weight) kernel only; ignored by the others
+    const uint32_t* ent;         // [npad][SCHED_DMAX] slot schedule of this layer
+    const int32_t* lane_neuron;  // [npad] neuron of each lane slot (-1: none)
+    const int32_t* wave_steps;   // [nblk] steps of each 64-neuron block
+    int32_t* tile_bits;          // [max tiles] row bits combined across neuron parts
+    int32_t* tile_cnt;           // [max tiles] parts finished per tile
+    int32_t parts;               // G: workgroups sharing a tile (each owns NT neurons)
+    int32_t nblk;                // 64-neuron blocks
 };
+
+constexpr int SCHED_T = 4;       // rows per tile of the scheduled kernel
+constexpr int SCHED_NT = 1024;   // its workgroup size
+constexpr int SCHED_DMAX = 44;   // most schedule steps a block may need
 
 // Whole forward pass run by the persistent kernel (all layers, one launch).
 struct ChainArgs {
@@ -56,6 +68,14 @@ struct ChainArgs {
     int32_t ckpt_every;
     int32_t compaction;
     float clamp;
+    // scheduled kernel only (stacked over layers)
+    const uint32_t* ent;         // [L][npad][SCHED_DMAX]
+    const int32_t* lane_neuron;  // [L][npad]
+    const int32_t* wave_steps;   // [L][nblk]
+    int32_t* tile_bits;
+    int32_t* tile_cnt;
+    int32_t parts;
+    int32_t nblk;
 };
 
 // Error codes written to the device error word.
@@ -65,13 +85,19 @@ enum DeviceError : int32_t { DEV_OK = 0, DEV_BARRIER_TIMEOUT = 1 };
 struct FwdVariant {
     int T;          // rows per tile
     int NT;         // threads per workgroup
-    int staged;     // 1 = rows staged in LDS, 0 = direct gather from global memory
+    int staged;     // 2 = scheduled resident-weight kernel, 1 = rows staged in LDS, 0 = direct gather
     const void* layer_fn;    // __global__ void(LayerArgs)
     const void* chain_fn;    // __global__ void(ChainArgs)  (cooperative)
 };
 int fwd_variant_count();
 const FwdVariant& fwd_variant(int i);
-inline size_t fwd_lds_bytes(const FwdVariant& v, int N) { return v.staged ? (size_t)v.T * N * sizeof(float) : 0; }
+inline size_t fwd_lds_bytes(const FwdVariant& v, int N) {
+    return v.staged == 2 ? (size_t)2 * SCHED_T * N * sizeof(float) : (v.staged ? (size_t)v.T * N * sizeof(float) : 0);
+}
+
+// Host-side slot scheduling (sdnn_sched.hip): see that file.
+int build_schedule(const int32_t* idx, int N, int L, int dmax, uint32_t* ent, int32_t* lane_neuron,
+                   int32_t* wave_steps);
 
 // Small kernels (sdnn_fwd.hip).
 __global__ void k_chain_init(int32_t* cnt, int32_t L, int32_t rows, int32_t compaction, unsigned* bar, int32_t nbar);

@@ -1,0 +1,217 @@
+// Create-time slot scheduling for the resident-weight forward kernel.
+//
+// The scheduled kernel stages 4 activation rows per tile in LDS, interleaved
+// [N][4], so the 4 values one input id feeds are one 16-byte slot (slot = id).
+// On gfx950 a 16-byte LDS read is served 16 lanes per cycle, in the lane units
+// {0-7, 24-31}, {8-15, 16-23}, {32-39, 56-63}, {40-47, 48-55}, against 64
+// banks: a unit's read is conflict-free iff its 16 lanes hit 16 distinct bank
+// groups (slot mod 16).  (Measured on the device: 16-byte reads whose units cover
+// all 16 groups run at the contiguous rate; any other grouping, or random ids,
+// runs 2-3x slower.)
+//
+// Each lane owns one neuron for a whole layer and may process its 32 slots in
+// any order.  For every block of 64 neurons (one wave) this file:
+//   1. balances the 64 neurons over the 4 units so that each unit's per-group
+//      slot counts are as even as possible (greedy + pairwise swaps): the number
+//      of steps a unit needs is at least its largest group count;
+//   2. schedules each unit greedily: at every step each lane takes a slot whose
+//      group no other lane of the unit uses in that step (the lane with most
+//      remaining slots picks first, its most frequent free group);
+//   3. pads every lane to the block's step count with dummy steps (weight 0) that
+//      read a group left free in that step, keeping every step conflict-free.
+// The summation order of a neuron is therefore its schedule order, fixed at
+// create time: results are deterministic and identical across engines.
+#include <algorithm>
+#include <array>
+#include <atomic>
+#include <cstdint>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "sdnn_internal.hpp"
+
+namespace sdnn {
+
+namespace {
+
+constexpr int NG = 16;        // bank groups of 16 bytes
+constexpr int UNITS = 4;      // lane units per wave
+constexpr int ULANES = 16;    // lanes per unit
+
+// wave lane of position q (0..15) in unit u
+inline int unit_lane(int u, int q) {
+    static const int base[UNITS][2] = {{0, 24}, {8, 16}, {32, 56}, {40, 48}};
+    return base[u][q / 8] + (q % 8);
+}
+
+struct Block {
+    int n = 0;                                  // real neurons in the block
+    std::array<std::array<int, NG>, 64> hist{};  // per neuron, slots per group
+};
+
+// assign 64 neuron slots (some phantom) to 4 units of 16 -> unit_of[64]
+void balance(const Block& B, std::array<int, 64>& members_out) {
+    std::array<int, 64> order;
+    for (int i = 0; i < 64; ++i) order[i] = i;
+    auto mx = [&](int i) { return *std::max_element(B.hist[i].begin(), B.hist[i].end()); };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return mx(a) > mx(b); });
+    std::array<std::array<int, NG>, UNITS> sum{};
+    std::array<std::vector<int>, UNITS> mem;
+    for (int i : order) {
+        int best = -1, bv = 1 << 30;
+        for (int u = 0; u < UNITS; ++u) {
+            if ((int)mem[u].size() >= ULANES) continue;
+            int v = 0;
+            for (int g = 0; g < NG; ++g) v = std::max(v, sum[u][g] + B.hist[i][g]);
+            if (v < bv) { bv = v; best = u; }
+        }
+        mem[best].push_back(i);
+        for (int g = 0; g < NG; ++g) sum[best][g] += B.hist[i][g];
+    }
+    auto umax = [&](int u) { return *std::max_element(sum[u].begin(), sum[u].end()); };
+    for (int it = 0; it < 400; ++it) {
+        int worst = 0;
+        for (int u = 1; u < UNITS; ++u)
+            if (umax(u) > umax(worst)) worst = u;
+        const int cur = umax(worst);
+        bool improved = false;
+        for (int a = 0; a < ULANES && !improved; ++a) {
+            for (int u = 0; u < UNITS && !improved; ++u) {
+                if (u == worst) continue;
+                for (int b = 0; b < ULANES && !improved; ++b) {
+                    const int ia = mem[worst][a], ib = mem[u][b];
+                    int nw = 0, nu = 0;
+                    for (int g = 0; g < NG; ++g) {
+                        nw = std::max(nw, sum[worst][g] - B.hist[ia][g] + B.hist[ib][g]);
+                        nu = std::max(nu, sum[u][g] - B.hist[ib][g] + B.hist[ia][g]);
+                    }
+                    if (std::max(nw, nu) < cur) {
+                        for (int g = 0; g < NG; ++g) {
+                            sum[worst][g] += B.hist[ib][g] - B.hist[ia][g];
+                            sum[u][g] += B.hist[ia][g] - B.hist[ib][g];
+                        }
+                        std::swap(mem[worst][a], mem[u][b]);
+                        improved = true;
+                    }
+                }
+            }
+        }
+        if (!improved) break;
+    }
+    for (int u = 0; u < UNITS; ++u)
+        for (int q = 0; q < ULANES; ++q) members_out[unit_lane(u, q)] = mem[u][q];
+}
+
+}  // namespace
+
+// Build the schedule of layers [l0, l1).  idx: host copy of all ids [L][N][K].
+// Output (host):
+//   ent[(l*npad + lane_slot)*dmax + s] = (id << 5) | k, or dummy (bit 31 set, id = free group)
+//   lane_neuron[l*npad + lane_slot]   = neuron computed by that lane slot, or -1
+//   wave_steps[l*nblk + b]            = steps of block b
+// Returns the largest step count seen (callers reject > dmax).
+int build_schedule_range(const int32_t* idx, int N, int l0, int l1, int dmax, uint32_t* ent, int32_t* lane_neuron,
+                         int32_t* wave_steps) {
+    const int nblk = (N + 63) / 64, npad = nblk * 64;
+    int worst = 0;
+    for (int l = l0; l < l1; ++l) {
+        const int32_t* il = idx + (size_t)l * N * K;
+        for (int b = 0; b < nblk; ++b) {
+            Block B;
+            B.n = std::min(64, N - 64 * b);
+            for (int i = 0; i < B.n; ++i)
+                for (int k = 0; k < K; ++k) B.hist[i][il[(size_t)(64 * b + i) * K + k] % NG]++;
+            std::array<int, 64> member;   // member[lane] = local neuron index 0..63 (>= n: phantom)
+            balance(B, member);
+            // per lane: list of slots k by group
+            std::array<std::array<std::vector<int>, NG>, 64> pend;
+            std::array<int, 64> left{};
+            for (int lane = 0; lane < 64; ++lane) {
+                const int i = member[lane];
+                if (i >= B.n) continue;
+                for (int k = 0; k < K; ++k) {
+                    pend[lane][il[(size_t)(64 * b + i) * K + k] % NG].push_back(k);
+                    ++left[lane];
+                }
+            }
+            // schedule every unit
+            std::array<std::vector<uint32_t>, 64> seq;
+            int steps_blk = 0;
+            for (int u = 0; u < UNITS; ++u) {
+                int lanes[ULANES];
+                for (int q = 0; q < ULANES; ++q) lanes[q] = unit_lane(u, q);
+                int remaining = 0;
+                for (int q = 0; q < ULANES; ++q) remaining += left[lanes[q]];
+                while (remaining > 0) {
+                    bool used[NG] = {};
+                    int pick[ULANES];
+                    int ord[ULANES];
+                    for (int q = 0; q < ULANES; ++q) ord[q] = q;
+                    std::stable_sort(ord, ord + ULANES, [&](int a, int c) { return left[lanes[a]] > left[lanes[c]]; });
+                    for (int oi = 0; oi < ULANES; ++oi) {
+                        const int q = ord[oi], lane = lanes[q];
+                        pick[q] = -1;
+                        int bg = -1, bc = 0;
+                        for (int g = 0; g < NG; ++g) {
+                            const int c = (int)pend[lane][g].size();
+                            if (c > bc && !used[g]) { bc = c; bg = g; }
+                        }
+                        if (bg >= 0) { used[bg] = true; pick[q] = bg; }
+                    }
+                    for (int q = 0; q < ULANES; ++q) {
+                        const int lane = lanes[q];
+                        if (pick[q] >= 0) {
+                            const int g = pick[q];
+                            const int k = pend[lane][g].back();
+                            pend[lane][g].pop_back();
+                            --left[lane];
+                            --remaining;
+                            const int32_t id = il[(size_t)(64 * b + member[lane]) * K + k];
+                            seq[lane].push_back(((uint32_t)id << 5) | (uint32_t)k);
+                        } else {
+                            int g = 0;
+                            while (used[g]) ++g;
+                            used[g] = true;
+                            seq[lane].push_back(0x80000000u | ((uint32_t)g << 5) | 31u);
+                        }
+                    }
+                }
+                steps_blk = std::max(steps_blk, (int)seq[lanes[0]].size());
+            }
+            // pad to the block's step count: all 16 lanes of a unit take distinct groups
+            for (int u = 0; u < UNITS; ++u)
+                for (int q = 0; q < ULANES; ++q) {
+                    auto& s = seq[unit_lane(u, q)];
+                    while ((int)s.size() < steps_blk) s.push_back(0x80000000u | ((uint32_t)q << 5) | 31u);
+                }
+            worst = std::max(worst, steps_blk);
+            wave_steps[(size_t)l * nblk + b] = steps_blk;
+            for (int lane = 0; lane < 64; ++lane) {
+                const size_t slot = (size_t)l * npad + 64 * b + lane;
+                lane_neuron[slot] = member[lane] < B.n ? 64 * b + member[lane] : -1;
+                for (int s = 0; s < dmax; ++s)
+                    ent[slot * dmax + s] = s < (int)seq[lane].size() ? seq[lane][s] : (0x80000000u | 31u);
+            }
+        }
+    }
+    return worst;
+}
+
+int build_schedule(const int32_t* idx, int N, int L, int dmax, uint32_t* ent, int32_t* lane_neuron,
+                   int32_t* wave_steps) {
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    nth = std::min<unsigned>(nth, (unsigned)L);
+    std::vector<std::thread> th;
+    std::vector<int> worst(nth, 0);
+    for (unsigned t = 0; t < nth; ++t) {
+        const int l0 = (int)((int64_t)L * t / nth), l1 = (int)((int64_t)L * (t + 1) / nth);
+        th.emplace_back([=, &worst] {
+            worst[t] = build_schedule_range(idx, N, l0, l1, dmax, ent, lane_neuron, wave_steps);
+        });
+    }
+    for (auto& x : th) x.join();
+    return *std::max_element(worst.begin(), worst.end());
+}
+
+}  // namespace sdnn

@@ -53,6 +53,7 @@ PROTOTYPES = [
     ("sdnn_backward", _I32, [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
     ("sdnn_layer_backward", _I32, [_P, _I32, _P, _P, _P, _I64, _P, _P, _P, _P]),
     ("sdnn_mse", _I32, [_P, _P, _I64, _P, _P, _P]),
+    ("sdnn_schedule_host", _I32, [_P, _I32, _I32, _I32, _P, _P, _P]),
     ("sdnn_check_device", _I32, [_P, _P]),
     ("sdnn_destroy", None, [_P]),
     ("sdnn_last_error", ctypes.c_char_p, []),
@@ -165,6 +166,22 @@ def sdnn_layer_backward(h, layer, y_in, y_out, dy_out, rows, dw, dbias, dy_in=No
 
 def sdnn_mse(y, t, n, dy=None, loss=None, stream=None) -> None:
     _chk(lib().sdnn_mse(_ptr(y), _ptr(t), n, _ptr(dy), _ptr(loss), _stream(stream)), "sdnn_mse")
+
+
+def sdnn_schedule_host(idx, dmax: int = 44):
+    """Host slot schedule for an int32 numpy array idx [L][N][k] -> (worst, ent, lane_neuron, steps)."""
+    import numpy as np
+    idx = np.ascontiguousarray(idx, np.int32)
+    L, N, _ = idx.shape
+    nblk = (N + 63) // 64
+    ent = np.zeros((L, nblk * 64, dmax), np.uint32)
+    ln = np.zeros((L, nblk * 64), np.int32)
+    st = np.zeros((L, nblk), np.int32)
+    worst = lib().sdnn_schedule_host(idx.ctypes.data_as(_P), N, L, dmax, ent.ctypes.data_as(_P),
+                                     ln.ctypes.data_as(_P), st.ctypes.data_as(_P))
+    if worst < 0:
+        raise SdnnError(worst, "sdnn_schedule_host")
+    return worst, ent, ln, st
 
 
 def sdnn_check_device(h, stream=None) -> None:

@@ -1,0 +1,64 @@
+"""CPU checks of the create-time slot scheduler of the resident-weight kernel."""
+import numpy as np
+import pytest
+
+import sdnn_inputs as gen
+
+UNITS = [list(range(0, 8)) + list(range(24, 32)), list(range(8, 16)) + list(range(16, 24)),
+         list(range(32, 40)) + list(range(56, 64)), list(range(40, 48)) + list(range(48, 56))]
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2004_10908_amd as p
+    return p
+
+
+@pytest.mark.parametrize("N,L,seed", [(4096, 3, 1), (1024, 4, 2), (96, 2, 3), (2048, 2, 4)])
+def test_schedule_invariants(P, N, L, seed):
+    cfg = gen.tiny_config(N, L, 1, seed)
+    idx = np.stack([gen.make_layer(cfg, l)[0] for l in range(L)])
+    dmax = 44
+    worst, ent, ln, steps = P.sdnn_schedule_host(idx, dmax)
+    assert worst <= dmax
+    nblk = (N + 63) // 64
+    for l in range(L):
+        seen = np.zeros(N, bool)
+        for b in range(nblk):
+            D = steps[l, b]
+            lower = 32
+            for lane in range(64):
+                j = ln[l, 64 * b + lane]
+                e = ent[l, 64 * b + lane, :D]
+                real = e[(e >> 31) == 0]
+                if j < 0:
+                    assert real.size == 0
+                    continue
+                assert 64 * b <= j < 64 * b + 64 and not seen[j]
+                seen[j] = True
+                ks = (real & 31).astype(int)
+                ids = (real >> 5).astype(int)
+                assert sorted(ks) == list(range(32)), "each slot exactly once"
+                assert np.array_equal(ids, idx[l, j, ks]), "entry id matches its slot"
+                assert ((ent[l, 64 * b + lane, D:] >> 31) == 1).all()
+            for u in UNITS:
+                for s in range(D):
+                    g = (ent[l, 64 * b + np.array(u), s] >> 5) % 16
+                    assert len(set(g.tolist())) == 16, "a step of a unit must hit 16 bank groups"
+            # balanced units need at least as many steps as their busiest bank group
+            for u in UNITS:
+                js = [ln[l, 64 * b + lane] for lane in u if ln[l, 64 * b + lane] >= 0]
+                if js:
+                    h = np.bincount((idx[l, js] % 16).ravel(), minlength=16)
+                    lower = max(lower, h.max())
+            assert lower <= D <= lower + 4
+        assert seen.all()
+    if N == 4096:
+        assert steps.mean() < 39.5        # balancing keeps the padding near 20%
+
+
+def test_schedule_rejects_bad_ids(P):
+    idx = np.zeros((1, 64, 32), np.int32)
+    idx[0, 0, 0] = 64
+    with pytest.raises(P.SdnnError):
+        P.sdnn_schedule_host(idx)
