@@ -90,7 +90,7 @@ Layout make_layout(const sdnn_desc& d) {
     y.sched = sched_possible(d);
     if (y.sched) {
         const size_t nblk = (N + 63) / 64, npad = nblk * 64;
-        y.ent = take(L * npad * SCHED_DMAX * 4);
+        y.ent = take(L * npad * SCHED_DSTORE * 4);
         y.lane_neuron = take(L * npad * 4);
         y.wave_steps = take(L * nblk * 4);
         y.tile_bits = take(((R + SCHED_T - 1) / SCHED_T) * 4);
@@ -211,7 +211,7 @@ bool variant_fits(const sdnn_net_s* n, const FwdVariant& v) {
 void fill_sched(const sdnn_net_s* n, LayerArgs& a, int l) {
     if (!n->sched) return;
     const size_t npad = (size_t)n->nblk * 64;
-    a.ent = n->ent + (size_t)l * npad * SCHED_DMAX;
+    a.ent = n->ent + (size_t)l * npad * SCHED_DSTORE;
     a.lane_neuron = n->lane_neuron + (size_t)l * npad;
     a.wave_steps = n->wave_steps + (size_t)l * n->nblk;
     a.tile_bits = n->tile_bits;
@@ -549,10 +549,15 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
         bool ids_ok = true;
         for (size_t i = 0; i < hidx.size() && ids_ok; ++i) ids_ok = hidx[i] >= 0 && hidx[i] < N;
         if (ids_ok) {
-            std::vector<uint32_t> hent((size_t)L * npad * SCHED_DMAX);
+            std::vector<uint32_t> hent((size_t)L * npad * SCHED_DSTORE);
             std::vector<int32_t> hln((size_t)L * npad), hws((size_t)L * n->nblk);
-            const int worst = build_schedule(hidx.data(), N, L, SCHED_DMAX, hent.data(), hln.data(), hws.data());
-            if (worst <= SCHED_DMAX) {
+            const int worst = build_schedule(hidx.data(), N, L, SCHED_DSTORE, hent.data(), hln.data(), hws.data());
+            if (worst <= SCHED_DSTORE) {
+                // the kernel wants LDS byte offsets: id -> 512 (id / 16) + 16 (id % 16)
+                for (auto& e : hent) {
+                    const uint32_t id = (e >> 5) & 0x03ffffffu;
+                    e = (e & 0x8000001fu) | ((((id >> 4) << 9) | ((id & 15u) << 4)) << 5);
+                }
                 HIPCHK(hipMemcpyAsync(n->ent, hent.data(), hent.size() * 4, hipMemcpyHostToDevice, s));
                 HIPCHK(hipMemcpyAsync(n->lane_neuron, hln.data(), hln.size() * 4, hipMemcpyHostToDevice, s));
                 HIPCHK(hipMemcpyAsync(n->wave_steps, hws.data(), hws.size() * 4, hipMemcpyHostToDevice, s));

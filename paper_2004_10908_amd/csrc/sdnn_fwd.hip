@@ -186,8 +186,8 @@ __global__ __launch_bounds__(NT) void k_layer(LayerArgs a) {
 // bar layout (one 128-byte line each): [g*32] group g, [8*32] root, [9*32] generation.
 
 
-__device__ bool grid_barrier(unsigned* bar, unsigned& gen, int32_t* err) {
-    __shared__ int s_ok;
+__device__ bool grid_barrier(unsigned* bar, unsigned& gen, int32_t* err, int* s_ok_ptr) {
+    int& s_ok = *s_ok_ptr;
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned nwg = gridDim.x;
@@ -277,6 +277,7 @@ __global__ __launch_bounds__(FIN_NT) void k_finalize(const int32_t* alive, int32
 template <int T, int NT, bool STAGED>
 __global__ __launch_bounds__(NT) void k_chain(ChainArgs c) {
     extern __shared__ __align__(16) float lds[];
+    __shared__ int s_ok;
     unsigned gen = 0u;
     const int N = c.N, L = c.L;
     const size_t NK = (size_t)N * K;
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(NT) void k_chain(ChainArgs c) {
         a.layer = l;
         a.clamp = c.clamp;
         run_layer<T, NT, STAGED>(a, lds, blockIdx.x, gridDim.x, R);
-        if (!grid_barrier(c.bar, gen, c.err)) return;
+        if (!grid_barrier(c.bar, gen, c.err, &s_ok)) return;
     }
     // the nz list and the row profile are produced by a k_finalize launch after this kernel
 }
@@ -324,16 +325,111 @@ __global__ __launch_bounds__(NT) void k_chain(ChainArgs c) {
 // the alive rows, writes the alive flags and zeroes dead rows where needed.
 // Workgroup b serves part (b/8) % G of tile stream (b/(8G))*8 + b%8, so the parts
 // of a tile run on the same XCD (blockIdx % 8) and share its L2.
+// LDS layout: the two tile buffers are interleaved in 256-byte blocks, block m of
+// buffer b at byte (2m + b) * 256; ids 16m .. 16m+15 of a 4-row tile fill block m
+// ([id][row], 16 bytes per id).  An id's byte offset in buffer 0 is
+// 512 (id / 16) + 16 (id % 16); buffer 1 is the same plus an immediate 256, so the
+// per-step offset registers serve both buffers and the bank group (16-byte slot
+// mod 16) is id mod 16 in either.
+__device__ __forceinline__ uint32_t sched_off(uint32_t id) { return ((id >> 4) << 9) | ((id & 15u) << 4); }
+
+// 16-byte LDS read at an absolute LDS byte address (the offsets already include
+// the workgroup's LDS base), so the address register is used as is.
+__device__ __forceinline__ float4 lds_read16(uint32_t addr) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    __builtin_assume((addr & 15u) == 0u);
+    const v4f r = *reinterpret_cast<const v4f __attribute__((address_space(3)))*>(addr);
+    return make_float4(r.x, r.y, r.z, r.w);
+#else
+    (void)addr;   // host pass of a device-only function
+    return make_float4(0.f, 0.f, 0.f, 0.f);
+#endif
+}
+
+template <int DMAX, int BUF>
+__device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_base, const uint32_t (&off)[DMAX],
+                                            const float (&wv)[DMAX], int D, int slot, int j, float (&acc)[SCHED_T]) {
+    // Steps in groups of 4; the reads of group g+1 are issued before the FMAs of
+    // group g (ping-pong register sets).  Steps past D are padding (id 0, weight 0:
+    // a broadcast read), so reading one group ahead is always safe.
+    static_assert(DMAX % 4 == 0, "groups of 4");
+    float4 v[2][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[0][u] = lds_read16(off[u] + BUF * 256);
+#pragma unroll
+    for (int g = 0; g < DMAX / 4; ++g) {
+        if (4 * g < D) {
+            if (g + 1 < DMAX / 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[(g + 1) & 1][u] = lds_read16(off[4 * (g + 1) + u] + BUF * 256);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int st = 4 * g + u;
+                const float4 c = v[g & 1][u];
+                acc[0] = fmaf(wv[st], c.x, acc[0]);
+                acc[1] = fmaf(wv[st], c.y, acc[1]);
+                acc[2] = fmaf(wv[st], c.z, acc[2]);
+                acc[3] = fmaf(wv[st], c.w, acc[3]);
+            }
+        }
+    }
+    if (D > DMAX) {
+        // rare blocks with a longer schedule: remaining steps come from memory
+        for (int st = DMAX; st < D; ++st) {
+            const uint32_t e = a.ent[(size_t)slot * SCHED_DSTORE + st];
+            const float w = ((e & 0x80000000u) || j < 0) ? 0.f : a.w[(size_t)j * K + (e & 31u)];
+            const float4 c = lds_read16(lds_base + ((e >> 5) & 0x03ffffffu) + BUF * 256);
+            acc[0] = fmaf(w, c.x, acc[0]);
+            acc[1] = fmaf(w, c.y, acc[1]);
+            acc[2] = fmaf(w, c.z, acc[2]);
+            acc[3] = fmaf(w, c.w, acc[3]);
+        }
+    }
+}
+
+// One lane's resident neuron: schedule offsets and weights of one 64-neuron block.
+template <int DMAX>
+struct SchedNeuron {
+    uint32_t off[DMAX];
+    float wv[DMAX];
+    int D, slot, j;
+    float bj;
+    __device__ __forceinline__ void load(const LayerArgs& a, int blk, int lane, uint32_t lds_base) {
+        const bool have = blk < a.nblk;
+        slot = blk * 64 + lane;
+        j = have ? a.lane_neuron[slot] : -1;
+        D = have ? __builtin_amdgcn_readfirstlane(a.wave_steps[blk]) : 0;
+        // entries hold the LDS byte offset of the slot's id (see sched_off) and the slot;
+        // all loads are issued before any is waited for
+        uint32_t e[DMAX];
+#pragma unroll
+        for (int st = 0; st < DMAX; ++st)
+            e[st] = (have && st < D) ? a.ent[(size_t)slot * SCHED_DSTORE + st] : (0x80000000u | 31u);
+#pragma unroll
+        for (int st = 0; st < DMAX; ++st) {
+            off[st] = lds_base + ((e[st] >> 5) & 0x03ffffffu);
+            wv[st] = ((e[st] & 0x80000000u) || j < 0) ? 0.f : a.w[(size_t)j * K + (e[st] & 31u)];
+        }
+#pragma unroll
+        for (int st = 0; st < DMAX; ++st) __asm__ volatile("" : "+v"(off[st]), "+v"(wv[st]));   // keep resident
+        bj = j >= 0 ? a.b[j] : 0.f;
+    }
+};
+
 template <int NT, int DMAX>
 __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __restrict__ lds, int R) {
     constexpr int T = SCHED_T;
-    __shared__ unsigned s_bits[2];
-    __shared__ unsigned s_final;
-    __shared__ int s_last;
+    constexpr int WAVES = NT / 64;
     const int N = a.N;
+    // the workgroup's LDS: two interleaved tile buffers (2 * 4 * N floats), then 4 words
+    unsigned* s_bits = reinterpret_cast<unsigned*>(lds + 2 * T * N);   // [2]
+    unsigned& s_final = s_bits[2];
+    int& s_last = reinterpret_cast<int&>(s_bits[3]);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int G = a.parts;
     const int b = blockIdx.x;
     const int x = b & 7, kk = b >> 3;
@@ -342,42 +438,50 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
     const int S = (int)gridDim.x / G;
     const int ntiles = (R + T - 1) / T;
     if (q >= ntiles) return;                         // uniform over the workgroup
-    const int blk = p * (NT / 64) + wave;
-    const bool have = blk < a.nblk;
-    const int slot = blk * 64 + lane;
-    const int j = have ? a.lane_neuron[slot] : -1;
-    const int D = have ? __builtin_amdgcn_readfirstlane(a.wave_steps[blk]) : 0;
-    uint32_t off[DMAX];
-    float wv[DMAX];
-#pragma unroll
-    for (int st = 0; st < DMAX; ++st) {
-        const uint32_t e = (have && st < D) ? a.ent[(size_t)slot * DMAX + st] : (0x80000000u | 31u);
-        off[st] = ((e >> 5) & 0x03ffffffu) * (T * 4);
-        wv[st] = ((e & 0x80000000u) || j < 0) ? 0.f : a.w[(size_t)j * K + (e & 31u)];
-    }
-    const float bj = j >= 0 ? a.b[j] : 0.f;
-    const int nchunks = (T * N) / 64;                // 64 floats (16 ids x 4 rows) per chunk
+    // a part is 16 blocks of 64 neurons; wave w owns blocks 2w and 2w + 1 of it
+    const uint32_t lds_base = (uint32_t)(uintptr_t)lds;
+    SchedNeuron<DMAX> n0, n1;
+    n0.load(a, p * 16 + 2 * wave, lane, lds_base);
+    n1.load(a, p * 16 + 2 * wave + 1, lane, lds_base);
+    // staging: chunk c (ids 16c .. 16c+15, 4 rows, 256 bytes) is loaded by wave c % WAVES;
+    // lane l holds row l % 4 of id 16c + l / 4, so a wave's LDS store is 256 contiguous bytes
+    const int nchunks = N / 16;
     auto row_of = [&](int tile, int t) {
         const int pos = tile * T + t;
         const int pp = pos < R ? pos : tile * T;     // padding rows repeat the tile's first row
         return a.list_in ? a.list_in[pp] : a.row_base + pp;
     };
+    // Asynchronous global->LDS copies (each lane's dword lands at M0 + 4 * lane).
+    // Issued from inline asm so the compiler does not make every LDS read wait for
+    // them; the wait is explicit: s_waitcnt vmcnt(0) + barrier before a buffer is read.
     auto stage = [&](int tile, int buf) {
         const float* src = a.yin + (size_t)row_of(tile, lane & 3) * N + (lane >> 2);
-        float* dst = lds + (size_t)buf * T * N;
-        for (int c = wave; c < nchunks; c += NT / 64)
-            __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(src + 16 * c),
-                                             (void __attribute__((address_space(3)))*)(dst + 64 * c), 4, 0, 0);
+        for (int c = wave; c < nchunks; c += WAVES) {
+            const uint32_t dst = __builtin_amdgcn_readfirstlane(lds_base + 512u * c + 256u * buf);
+            const float* g = src + 16 * c;
+            uint32_t saved;
+            __asm__ volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\tglobal_load_lds_dword %1, off\n\ts_mov_b32 m0, %0"
+                             : "=&s"(saved) : "v"(g), "s"(dst) : "memory");
+        }
     };
     if (tid == 0) { s_bits[0] = 0u; s_bits[1] = 0u; }
+    stage(q, 0);
     int it = 0;
-    if (q < ntiles) stage(q, 0);
     for (int tile = q; tile < ntiles; tile += S, ++it) {
         const int buf = it & 1;
-        __builtin_amdgcn_s_waitcnt(0);
+        __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
         __syncthreads();
-        if (tile + S < ntiles) stage(tile + S, buf ^ 1);
+        const bool more = tile + S < ntiles;
+        if (more) stage(tile + S, buf ^ 1);
         if (tid == 0) s_bits[buf ^ 1] = 0u;
+        float acc0[T] = {0.f, 0.f, 0.f, 0.f}, acc1[T] = {0.f, 0.f, 0.f, 0.f};
+        if (buf == 0) {
+            sched_steps<DMAX, 0>(a, lds_base, n0.off, n0.wv, n0.D, n0.slot, n0.j, acc0);
+            sched_steps<DMAX, 0>(a, lds_base, n1.off, n1.wv, n1.D, n1.slot, n1.j, acc1);
+        } else {
+            sched_steps<DMAX, 1>(a, lds_base, n0.off, n0.wv, n0.D, n0.slot, n0.j, acc0);
+            sched_steps<DMAX, 1>(a, lds_base, n1.off, n1.wv, n1.D, n1.slot, n1.j, acc1);
+        }
         int rr[T];
         bool vr[T];
 #pragma unroll
@@ -385,23 +489,15 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
             vr[t] = tile * T + t < R;
             rr[t] = row_of(tile, t);
         }
-        const char* L4 = reinterpret_cast<const char*>(lds + (size_t)buf * T * N);
-        float acc[T] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int st = 0; st < DMAX; ++st) {
-            if (st < D) {
-                const float4 v = *reinterpret_cast<const float4*>(L4 + off[st]);
-                acc[0] = fmaf(wv[st], v.x, acc[0]);
-                acc[1] = fmaf(wv[st], v.y, acc[1]);
-                acc[2] = fmaf(wv[st], v.z, acc[2]);
-                acc[3] = fmaf(wv[st], v.w, acc[3]);
-            }
-        }
         unsigned bits = 0u;
-        if (j >= 0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int j = h ? n1.j : n0.j;
+            const float bj = h ? n1.bj : n0.bj;
+            if (j < 0) continue;
 #pragma unroll
             for (int t = 0; t < T; ++t) {
-                const float y = fminf(fmaxf(acc[t] + bj, 0.f), a.clamp);
+                const float y = fminf(fmaxf((h ? acc1[t] : acc0[t]) + bj, 0.f), a.clamp);
                 if (vr[t]) {
                     const size_t o = (size_t)rr[t] * N + j;
                     a.yout[o] = y;
@@ -410,59 +506,60 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
                 }
             }
         }
-        if (!a.list_out && !a.alive) continue;      // recompute / single layer: no liveness
+        if (a.list_out || a.alive) {
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o);
-        if (lane == 0 && bits) atomicOr(&s_bits[buf], bits);
-        __syncthreads();
-        if (tid == 0) {
-            unsigned all = s_bits[buf];
-            int last = 1;
-            if (G > 1) {
-                atomicOr(&a.tile_bits[tile], (int)all);
-                __threadfence();
-                last = atomicAdd(&a.tile_cnt[tile], 1) == G - 1;
-                if (last) {
+            for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o);
+            if (lane == 0 && bits) atomicOr(&s_bits[buf], bits);
+            __syncthreads();
+            if (tid == 0) {
+                unsigned all = s_bits[buf];
+                int last = 1;
+                if (G > 1) {
+                    atomicOr(&a.tile_bits[tile], (int)all);
                     __threadfence();
-                    all = (unsigned)atomicOr(&a.tile_bits[tile], 0);
-                    atomicExch(&a.tile_bits[tile], 0);
-                    atomicExch(&a.tile_cnt[tile], 0);
+                    last = atomicAdd(&a.tile_cnt[tile], 1) == G - 1;
+                    if (last) {
+                        __threadfence();
+                        all = (unsigned)atomicOr(&a.tile_bits[tile], 0);
+                        atomicExch(&a.tile_bits[tile], 0);
+                        atomicExch(&a.tile_cnt[tile], 0);
+                    }
                 }
-            }
-            if (last && a.list_out) {
-                int n = 0;
+                if (last && a.list_out) {
+                    int n = 0;
 #pragma unroll
-                for (int t = 0; t < T; ++t) n += (vr[t] && ((all >> t) & 1u)) ? 1 : 0;
-                if (n) {
-                    int base = atomicAdd(a.cnt_out, n);
+                    for (int t = 0; t < T; ++t) n += (vr[t] && ((all >> t) & 1u)) ? 1 : 0;
+                    if (n) {
+                        int base = atomicAdd(a.cnt_out, n);
+#pragma unroll
+                        for (int t = 0; t < T; ++t)
+                            if (vr[t] && ((all >> t) & 1u)) a.list_out[base++] = rr[t];
+                    }
+                }
+                s_final = all;
+                s_last = last;
+            }
+            __syncthreads();
+            if (s_last) {
+                const unsigned all = s_final;
+                if (a.alive && tid < T) {
 #pragma unroll
                     for (int t = 0; t < T; ++t)
-                        if (vr[t] && ((all >> t) & 1u)) a.list_out[base++] = rr[t];
+                        if (t == tid && vr[t]) a.alive[rr[t]] = (int32_t)((all >> t) & 1u);
                 }
-            }
-            s_final = all;
-            s_last = last;
-        }
-        __syncthreads();
-        if (s_last) {
-            const unsigned all = s_final;
-            if (a.alive && tid < T && vr[tid < T ? tid : 0]) {
+                if (a.yzero) {
 #pragma unroll
-                for (int t = 0; t < T; ++t)
-                    if (t == tid) a.alive[rr[t]] = (int32_t)((all >> t) & 1u);
-            }
-            if (a.yzero) {
-#pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    if (vr[t] && !((all >> t) & 1u)) {
-                        float* z = a.yzero + (size_t)rr[t] * N;
-                        for (int i = tid; i < N; i += NT) z[i] = 0.f;
+                    for (int t = 0; t < T; ++t) {
+                        if (vr[t] && !((all >> t) & 1u)) {
+                            float* z = a.yzero + (size_t)rr[t] * N;
+                            for (int i = tid; i < N; i += NT) z[i] = 0.f;
+                        }
                     }
                 }
             }
         }
     }
-    __builtin_amdgcn_s_waitcnt(0);
+    __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
 }
 
 template <int NT, int DMAX>
@@ -503,7 +600,7 @@ __global__ __launch_bounds__(NT) void k_chain_sched(ChainArgs c) {
         a.N = N;
         a.layer = l;
         a.clamp = c.clamp;
-        a.ent = c.ent + (size_t)l * npad * DMAX;
+        a.ent = c.ent + (size_t)l * npad * SCHED_DSTORE;
         a.lane_neuron = c.lane_neuron + (size_t)l * npad;
         a.wave_steps = c.wave_steps + (size_t)l * c.nblk;
         a.tile_bits = c.tile_bits;
@@ -511,7 +608,7 @@ __global__ __launch_bounds__(NT) void k_chain_sched(ChainArgs c) {
         a.parts = c.parts;
         a.nblk = c.nblk;
         run_layer_sched<NT, DMAX>(a, lds, R);
-        if (!grid_barrier(c.bar, gen, c.err)) return;
+        if (!grid_barrier(c.bar, gen, c.err, reinterpret_cast<int*>(lds + 2 * SCHED_T * N) + 4)) return;
     }
 }
 

@@ -34,7 +34,7 @@ struct LayerArgs {
     int32_t layer;
     float clamp;
     // scheduled (resident-weight) kernel only; ignored by the others
-    const uint32_t* ent;         // [npad][SCHED_DMAX] slot schedule of this layer
+    const uint32_t* ent;         // [npad][SCHED_DSTORE] slot schedule of this layer
     const int32_t* lane_neuron;  // [npad] neuron of each lane slot (-1: none)
     const int32_t* wave_steps;   // [nblk] steps of each 64-neuron block
     int32_t* tile_bits;          // [max tiles] row bits combined across neuron parts
@@ -44,8 +44,9 @@ struct LayerArgs {
 };
 
 constexpr int SCHED_T = 4;       // rows per tile of the scheduled kernel
-constexpr int SCHED_NT = 1024;   // its workgroup size
-constexpr int SCHED_DMAX = 44;   // most schedule steps a block may need
+constexpr int SCHED_NT = 512;    // its workgroup size (each lane owns two neurons)
+constexpr int SCHED_DMAX = 40;   // schedule steps held in registers
+constexpr int SCHED_DSTORE = 64; // schedule steps stored per lane (steps past SCHED_DMAX are read from memory)
 
 // Whole forward pass run by the persistent kernel (all layers, one launch).
 struct ChainArgs {
@@ -69,7 +70,7 @@ struct ChainArgs {
     int32_t compaction;
     float clamp;
     // scheduled kernel only (stacked over layers)
-    const uint32_t* ent;         // [L][npad][SCHED_DMAX]
+    const uint32_t* ent;         // [L][npad][SCHED_DSTORE]
     const int32_t* lane_neuron;  // [L][npad]
     const int32_t* wave_steps;   // [L][nblk]
     int32_t* tile_bits;
@@ -92,7 +93,7 @@ struct FwdVariant {
 int fwd_variant_count();
 const FwdVariant& fwd_variant(int i);
 inline size_t fwd_lds_bytes(const FwdVariant& v, int N) {
-    return v.staged == 2 ? (size_t)2 * SCHED_T * N * sizeof(float) : (v.staged ? (size_t)v.T * N * sizeof(float) : 0);
+    return v.staged == 2 ? (size_t)2 * SCHED_T * N * sizeof(float) + 64 : (v.staged ? (size_t)v.T * N * sizeof(float) : 0);
 }
 
 // Host-side slot scheduling (sdnn_sched.hip): see that file.
