@@ -52,12 +52,14 @@ constexpr int P_GROUPS = 64;                    // backward row groups (dW parti
 constexpr int NBAR = BAR_WORDS;
 constexpr size_t LDS_BUDGET = 152 * 1024;       // dynamic LDS a layer tile may use
 constexpr int MSE_BLOCKS = 256;
+constexpr int SCHED_GRID = 256;                 // workgroups of the scheduled kernels (8 XCDs x 32)
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Layout {
     size_t act = 0, list0 = 0, list1 = 0, alive = 0, cnt = 0, bar = 0, err = 0, flag = 0;
     size_t ent = 0, lane_neuron = 0, wave_steps = 0, tile_bits = 0, tile_cnt = 0;
+    size_t ent_t = 0, ent_w = 0, lane_input = 0, steps_t = 0, gbuf2 = 0;
     bool sched = false;
     size_t tr_ptr = 0, tr_e = 0, seg = 0, gbuf0 = 0, gbuf1 = 0, pdw = 0, pdb = 0;
     size_t total = 0;
@@ -67,6 +69,8 @@ bool trainable(const sdnn_desc& d) { return (d.flags & SDNN_TRAINABLE) != 0; }
 
 // The scheduled resident-weight kernel needs two 4-row tiles in LDS, ids in
 // groups of 16, and at most 4 parts of 1024 neurons (grid of 256 = 8 XCDs x 32).
+int sched_parts(const sdnn_desc& d) { return ((d.n_neurons + 63) / 64 + 15) / 16; }
+
 bool sched_possible(const sdnn_desc& d) {
     const int nblk = (d.n_neurons + 63) / 64;
     const int G = (nblk + 15) / 16;
@@ -105,8 +109,18 @@ Layout make_layout(const sdnn_desc& d) {
         y.seg = take((size_t)(d.ckpt_every + 1) * R * N * 4);
         y.gbuf0 = take(std::max<size_t>(R, 2) * N * 4);   // also create-time scratch for 2N ints
         y.gbuf1 = take(R * N * 4);
-        y.pdw = take((size_t)P_GROUPS * N * K * 4);
-        y.pdb = take((size_t)P_GROUPS * N * 4);
+        // dW/db partials: 64 row groups, or one per tile stream of the scheduled kernel
+        const size_t groups = std::max<size_t>(P_GROUPS, y.sched ? (size_t)SCHED_GRID / sched_parts(d) : 0);
+        y.pdw = take(groups * N * K * 4);
+        y.pdb = take(groups * N * 4);
+        if (y.sched) {
+            const size_t nblk = (N + 63) / 64, npad = nblk * 64;
+            y.ent_t = take(L * npad * SCHED_DSTORE * 4);
+            y.ent_w = take(L * npad * SCHED_DSTORE * 4);
+            y.lane_input = take(L * npad * 4);
+            y.steps_t = take(L * nblk * 4);
+            y.gbuf2 = take(R * N * 4);
+        }
     }
     y.total = off;
     return y;
@@ -185,6 +199,10 @@ struct sdnn_net_s {
     uint32_t* ent = nullptr;
     int32_t *lane_neuron = nullptr, *wave_steps = nullptr, *tile_bits = nullptr, *tile_cnt = nullptr;
     int parts = 1, nblk = 0;
+    bool sched_bwd = false;             // transposed schedule built (scheduled backward)
+    uint32_t *ent_t = nullptr, *ent_w = nullptr;
+    int32_t *lane_input = nullptr, *steps_t = nullptr;
+    float* gbuf2 = nullptr;
     int exec = SDNN_EXEC_AUTO;
     int variant = 0;
     int grid = 0;
@@ -238,6 +256,13 @@ sdnn_status prepare_variant(sdnn_net_s* n, int vi, int* grid, int* chain_grid) {
     if (occ < 1 || occc < 1) return fail(SDNN_EUNSUPPORTED, "kernel variant T=%d NT=%d does not fit a CU", v.T, v.NT);
     *grid = n->num_cu * occ;
     *chain_grid = n->num_cu * occc;
+    if (v.staged == 2) {
+        // the scheduled kernels map workgroups to (XCD, part, stream): 8 * parts must divide the grid
+        if (*grid < SCHED_GRID || *chain_grid < SCHED_GRID)
+            return fail(SDNN_EUNSUPPORTED, "scheduled kernel needs %d co-resident workgroups", SCHED_GRID);
+        *grid = SCHED_GRID;
+        *chain_grid = SCHED_GRID;
+    }
     return SDNN_OK;
 }
 
@@ -414,6 +439,59 @@ int blocks_for(int64_t n, int per = 256, int cap = 4096) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(cap, (n + per - 1) / per));
 }
 
+// One layer of the scheduled backward: dW/db partials per tile stream (and the
+// masked gradient G), their fixed-order reduction, then the input gradient
+// through the transposed schedule (scattered to rows_out rows when given).
+sdnn_status backward_layer_sched(const sdnn_net_s* n, int l, const float* y_in, const float* y_out, const float* dy,
+                                 float* dy_in, const int32_t* rows_out, const int32_t* nrows, int64_t rows, float* dw_l,
+                                 float* db_l, hipStream_t s) {
+    const int N = n->d.n_neurons;
+    const size_t npad = (size_t)n->nblk * 64;
+    const size_t sh = (size_t)2 * SCHED_T * N * 4 + 64;
+    const int S = SCHED_GRID / n->parts;
+    SchedDwArgs da{};
+    da.y_in = y_in;
+    da.y_out = y_out;
+    da.dy = dy;
+    da.g_out = n->gbuf2;
+    da.nrows = nrows;
+    da.ent = n->ent + (size_t)l * npad * SCHED_DSTORE;
+    da.lane_neuron = n->lane_neuron + (size_t)l * npad;
+    da.wave_steps = n->wave_steps + (size_t)l * n->nblk;
+    da.pdw = n->pdw;
+    da.pdb = n->pdb;
+    da.N = N;
+    da.parts = n->parts;
+    da.nblk = n->nblk;
+    da.clamp = n->d.clamp;
+    void* dargs[] = {&da};
+    HIPCHK(hipLaunchKernel(bwd_dw_sched_fn(), dim3(SCHED_GRID), dim3(SCHED_NT), dargs, sh, s));
+    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for((int64_t)N * K + N)), dim3(256), 0, s, (const float*)n->pdw,
+                       (const float*)n->pdb, (int32_t)S, (int32_t)N, dw_l, db_l);
+    if (dy_in) {
+        LayerArgs a{};
+        a.yin = n->gbuf2;
+        a.yout = dy_in;
+        a.w = n->w + (size_t)l * N * K;
+        a.cnt_in = nrows;
+        a.N = N;
+        a.layer = l;
+        a.clamp = n->d.clamp;
+        a.ent = n->ent_t + (size_t)l * npad * SCHED_DSTORE;
+        a.ent_w = n->ent_w + (size_t)l * npad * SCHED_DSTORE;
+        a.lane_neuron = n->lane_input + (size_t)l * npad;
+        a.wave_steps = n->steps_t + (size_t)l * n->nblk;
+        a.parts = n->parts;
+        a.nblk = n->nblk;
+        a.rows_out = rows_out;
+        void* yargs[] = {&a};
+        HIPCHK(hipLaunchKernel(bwd_dy_sched_fn(), dim3(SCHED_GRID), dim3(SCHED_NT), yargs, sh, s));
+    }
+    (void)rows;
+    HIPCHK(hipGetLastError());
+    return SDNN_OK;
+}
+
 }  // namespace
 
 // ============================================================================ C ABI
@@ -567,6 +645,37 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
                 HIPCHK(hipGetLastError());
                 HIPCHK(hipStreamSynchronize(s));
                 n->sched = true;
+            }
+            if (n->sched && trainable(*desc)) {
+                // transposed schedule for the input-gradient gather: entries are edge
+                // positions j*K + k; the kernel wants the LDS offset of column j and the edge
+                std::vector<uint32_t> tent((size_t)L * npad * SCHED_DSTORE);
+                std::vector<int32_t> tln((size_t)L * npad), tws((size_t)L * n->nblk);
+                const int tworst =
+                    build_transposed_schedule(hidx.data(), N, L, SCHED_DSTORE, tent.data(), tln.data(), tws.data());
+                if (tworst <= SCHED_DSTORE) {
+                    std::vector<uint32_t> tw(tent.size());
+                    for (size_t i = 0; i < tent.size(); ++i) {
+                        const uint32_t e = tent[i] & 0x7fffffffu;
+                        const uint32_t col = e / K;
+                        tw[i] = e;
+                        tent[i] = (tent[i] & 0x80000000u) | ((((col >> 4) << 9) | ((col & 15u) << 4)) << 5);
+                    }
+                    n->ent_t = (uint32_t*)(n->ws + lay.ent_t);
+                    n->ent_w = (uint32_t*)(n->ws + lay.ent_w);
+                    n->lane_input = (int32_t*)(n->ws + lay.lane_input);
+                    n->steps_t = (int32_t*)(n->ws + lay.steps_t);
+                    n->gbuf2 = (float*)(n->ws + lay.gbuf2);
+                    HIPCHK(hipMemcpyAsync(n->ent_t, tent.data(), tent.size() * 4, hipMemcpyHostToDevice, s));
+                    HIPCHK(hipMemcpyAsync(n->ent_w, tw.data(), tw.size() * 4, hipMemcpyHostToDevice, s));
+                    HIPCHK(hipMemcpyAsync(n->lane_input, tln.data(), tln.size() * 4, hipMemcpyHostToDevice, s));
+                    HIPCHK(hipMemcpyAsync(n->steps_t, tws.data(), tws.size() * 4, hipMemcpyHostToDevice, s));
+                    HIPCHK(hipStreamSynchronize(s));
+                    const size_t sh = (size_t)2 * SCHED_T * N * 4 + 64;
+                    HIPCHK(hipFuncSetAttribute(bwd_dw_sched_fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+                    HIPCHK(hipFuncSetAttribute(bwd_dy_sched_fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+                    n->sched_bwd = true;
+                }
             }
         }
     }
@@ -808,6 +917,14 @@ sdnn_status sdnn_backward(sdnn_net net, const float* y0, int64_t rows, const flo
             HIPCHK(hipLaunchKernel(v.layer_fn, dim3(fgrid), dim3(v.NT), args, fsh, s));
         }
         for (int l = l1 - 1; l >= l0; --l) {
+            const bool sch = net->sched_bwd && var(net).staged == 2;
+            if (sch) {
+                TRY(backward_layer_sched(net, l, seg(l - l0), seg(l - l0 + 1), D, (l > 0 || dy0) ? (l == 0 ? dy0 : Dn) : nullptr,
+                                         l == 0 ? nz_rows : nullptr, n_nz, rows, dw + (size_t)l * NK,
+                                         dbias + (size_t)l * N, s));
+                if (l > 0 || dy0) std::swap(D, Dn);
+                continue;
+            }
             BwdDwArgs da{};
             da.y_in = seg(l - l0);
             da.y_out = seg(l - l0 + 1);
@@ -862,6 +979,9 @@ sdnn_status sdnn_layer_backward(sdnn_net net, int32_t layer, const float* y_in, 
     const size_t NK = (size_t)N * K;
     int32_t* nrows = net->flag + 2;                      // device copy of `rows`
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, nrows, (int64_t)1, (int32_t)rows);
+    if (net->sched_bwd && var(net).staged == 2)
+        return backward_layer_sched(net, layer, y_in, y_out, dy_out, rows > 0 ? dy_in : nullptr, nullptr, nrows, rows,
+                                    dw, dbias, s);
     const size_t bsh = (size_t)bwd_T() * N * 4;
     BwdDwArgs da{};
     da.y_in = y_in;

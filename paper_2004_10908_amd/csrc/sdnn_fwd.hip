@@ -379,7 +379,9 @@ __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_bas
         // rare blocks with a longer schedule: remaining steps come from memory
         for (int st = DMAX; st < D; ++st) {
             const uint32_t e = a.ent[(size_t)slot * SCHED_DSTORE + st];
-            const float w = ((e & 0x80000000u) || j < 0) ? 0.f : a.w[(size_t)j * K + (e & 31u)];
+            const bool pad = (e & 0x80000000u) || j < 0;
+            const float w = pad ? 0.f : (a.ent_w ? a.w[a.ent_w[(size_t)slot * SCHED_DSTORE + st]]
+                                                  : a.w[(size_t)j * K + (e & 31u)]);
             const float4 c = lds_read16(lds_base + ((e >> 5) & 0x03ffffffu) + BUF * 256);
             acc[0] = fmaf(w, c.x, acc[0]);
             acc[1] = fmaf(w, c.y, acc[1]);
@@ -410,15 +412,17 @@ struct SchedNeuron {
 #pragma unroll
         for (int st = 0; st < DMAX; ++st) {
             off[st] = lds_base + ((e[st] >> 5) & 0x03ffffffu);
-            wv[st] = ((e[st] & 0x80000000u) || j < 0) ? 0.f : a.w[(size_t)j * K + (e[st] & 31u)];
+            const bool pad = (e[st] & 0x80000000u) || j < 0;
+            wv[st] = pad ? 0.f : (a.ent_w ? a.w[a.ent_w[(size_t)slot * SCHED_DSTORE + st]]
+                                          : a.w[(size_t)j * K + (e[st] & 31u)]);
         }
 #pragma unroll
         for (int st = 0; st < DMAX; ++st) __asm__ volatile("" : "+v"(off[st]), "+v"(wv[st]));   // keep resident
-        bj = j >= 0 ? a.b[j] : 0.f;
+        bj = (j >= 0 && a.b) ? a.b[j] : 0.f;
     }
 };
 
-template <int NT, int DMAX>
+template <int NT, int DMAX, bool LINEAR = false>
 __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __restrict__ lds, int R) {
     constexpr int T = SCHED_T;
     constexpr int WAVES = NT / 64;
@@ -497,16 +501,18 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
             if (j < 0) continue;
 #pragma unroll
             for (int t = 0; t < T; ++t) {
-                const float y = fminf(fmaxf((h ? acc1[t] : acc0[t]) + bj, 0.f), a.clamp);
+                const float y = LINEAR ? (h ? acc1[t] : acc0[t])
+                                       : fminf(fmaxf((h ? acc1[t] : acc0[t]) + bj, 0.f), a.clamp);
                 if (vr[t]) {
-                    const size_t o = (size_t)rr[t] * N + j;
+                    const int ro = LINEAR && a.rows_out ? a.rows_out[tile * T + t] : rr[t];
+                    const size_t o = (size_t)ro * N + j;
                     a.yout[o] = y;
                     if (a.ycopy) a.ycopy[o] = y;
                     bits |= (y != 0.f ? 1u : 0u) << t;
                 }
             }
         }
-        if (a.list_out || a.alive) {
+        if (!LINEAR && (a.list_out || a.alive)) {
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o);
             if (lane == 0 && bits) atomicOr(&s_bits[buf], bits);
@@ -612,6 +618,147 @@ __global__ __launch_bounds__(NT) void k_chain_sched(ChainArgs c) {
     }
 }
 
+// Input gradient through the transposed pattern: the scheduled kernel in linear
+// mode (lane = input neuron, steps = its incoming edges, tile = the masked
+// gradient G of 4 rows, no bias / clamp / liveness).
+template <int NT, int DMAX>
+__global__ __launch_bounds__(NT) void k_bwd_dy_sched(LayerArgs a) {
+    extern __shared__ __align__(16) float lds[];
+    const int R = a.cnt_in ? *a.cnt_in : a.nrows;
+    run_layer_sched<NT, DMAX, true>(a, lds, R);
+}
+
+// Weight and bias gradients with the forward schedule.  Each lane owns two
+// neurons; for every step (one slot of its neuron) it keeps
+//   acc[st] = sum over its rows of G[r][j] * Y_l[r][id(st)]
+// (rows in ascending order within its tile stream), so a stream's partial sums
+// are deterministic.  The masked gradient G[r][j] = dY[r][j] [0 < Y_{l+1} < c]
+// of its neurons is also written out for the input-gradient pass.
+template <int NT, int DMAX>
+__global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
+    extern __shared__ __align__(16) float lds[];
+    constexpr int T = SCHED_T;
+    constexpr int WAVES = NT / 64;
+    const int N = a.N;
+    const int R = *a.nrows;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int G = a.parts;
+    const int b = blockIdx.x;
+    const int x = b & 7, kk = b >> 3;
+    const int p = kk % G;
+    const int q = (kk / G) * 8 + x;
+    const int S = (int)gridDim.x / G;
+    const int ntiles = (R + T - 1) / T;
+    const uint32_t lds_base = (uint32_t)(uintptr_t)lds;
+    int j[2], D[2], slot[2];
+    uint32_t off[2][DMAX];
+    float acc[2][DMAX];
+    float accb[2] = {0.f, 0.f};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int blk = p * 16 + 2 * wave + h;
+        const bool have = blk < a.nblk;
+        slot[h] = blk * 64 + lane;
+        j[h] = have ? a.lane_neuron[slot[h]] : -1;
+        D[h] = have ? __builtin_amdgcn_readfirstlane(a.wave_steps[blk]) : 0;
+        uint32_t e[DMAX];
+#pragma unroll
+        for (int st = 0; st < DMAX; ++st)
+            e[st] = (have && st < D[h]) ? a.ent[(size_t)slot[h] * SCHED_DSTORE + st] : (0x80000000u | 31u);
+#pragma unroll
+        for (int st = 0; st < DMAX; ++st) {
+            off[h][st] = lds_base + ((e[st] >> 5) & 0x03ffffffu);
+            acc[h][st] = 0.f;
+        }
+#pragma unroll
+        for (int st = 0; st < DMAX; ++st) __asm__ volatile("" : "+v"(off[h][st]));
+        // this stream's partials start at zero (steps past DMAX accumulate in memory)
+        if (j[h] >= 0) {
+            float* pw = a.pdw + ((size_t)q * N + j[h]) * K;
+#pragma unroll
+            for (int k = 0; k < K; ++k) pw[k] = 0.f;
+        }
+    }
+    const int nchunks = N / 16;
+    auto stage = [&](int tile, int buf) {
+        const int pos = tile * T + (lane & 3);
+        const float* src = a.y_in + (size_t)(pos < R ? pos : tile * T) * N + (lane >> 2);
+        for (int c = wave; c < nchunks; c += WAVES) {
+            const uint32_t dst = __builtin_amdgcn_readfirstlane(lds_base + 512u * c + 256u * buf);
+            const float* gp = src + 16 * c;
+            uint32_t saved;
+            __asm__ volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\tglobal_load_lds_dword %1, off\n\ts_mov_b32 m0, %0"
+                             : "=&s"(saved) : "v"(gp), "s"(dst) : "memory");
+        }
+    };
+    int it = 0;
+    if (q < ntiles) stage(q, 0);
+    for (int tile = q; tile < ntiles; tile += S, ++it) {
+        const int buf = it & 1;
+        __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
+        __syncthreads();
+        if (tile + S < ntiles) stage(tile + S, buf ^ 1);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            float g[T];
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const int r = tile * T + t;
+                g[t] = 0.f;
+                if (r < R && j[h] >= 0) {
+                    const size_t o = (size_t)r * N + j[h];
+                    const float yo = a.y_out[o];
+                    g[t] = (yo > 0.f && yo < a.clamp) ? a.dy[o] : 0.f;
+                    a.g_out[o] = g[t];
+                }
+                accb[h] += g[t];
+            }
+#pragma unroll
+            for (int st = 0; st < DMAX; ++st) {
+                if (st < D[h]) {
+                    const float4 v = buf == 0 ? lds_read16(off[h][st]) : lds_read16(off[h][st] + 256);
+                    float s = acc[h][st];
+                    s = fmaf(g[0], v.x, s);
+                    s = fmaf(g[1], v.y, s);
+                    s = fmaf(g[2], v.z, s);
+                    s = fmaf(g[3], v.w, s);
+                    acc[h][st] = s;
+                }
+            }
+            if (D[h] > DMAX && j[h] >= 0) {
+                float* pw = a.pdw + ((size_t)q * N + j[h]) * K;
+                for (int st = DMAX; st < D[h]; ++st) {
+                    const uint32_t e = a.ent[(size_t)slot[h] * SCHED_DSTORE + st];
+                    if (e & 0x80000000u) continue;
+                    const float4 v = lds_read16(lds_base + ((e >> 5) & 0x03ffffffu) + 256u * buf);
+                    float s = pw[e & 31u];
+                    s = fmaf(g[0], v.x, s);
+                    s = fmaf(g[1], v.y, s);
+                    s = fmaf(g[2], v.z, s);
+                    s = fmaf(g[3], v.w, s);
+                    pw[e & 31u] = s;
+                }
+            }
+        }
+    }
+    __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (j[h] < 0) continue;
+        float* pw = a.pdw + ((size_t)q * N + j[h]) * K;
+#pragma unroll
+        for (int st = 0; st < DMAX; ++st) {
+            if (st < D[h]) {
+                const uint32_t e = a.ent[(size_t)slot[h] * SCHED_DSTORE + st];
+                if (!(e & 0x80000000u)) pw[e & 31u] = acc[h][st];
+            }
+        }
+        a.pdb[(size_t)q * N + j[h]] = accb[h];
+    }
+}
+
 // ---------------------------------------------------------------- small kernels
 __global__ void k_chain_init(int32_t* cnt, int32_t L, int32_t rows, int32_t compaction, unsigned* bar, int32_t nbar) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= L; i += gridDim.x * blockDim.x)
@@ -705,6 +852,8 @@ static const FwdVariant g_variants[] = {
 #undef SDNN_VD
 
 int fwd_variant_count() { return (int)(sizeof(g_variants) / sizeof(g_variants[0])); }
+const void* bwd_dw_sched_fn() { return (const void*)&k_bwd_dw_sched<SCHED_NT, SCHED_DMAX>; }
+const void* bwd_dy_sched_fn() { return (const void*)&k_bwd_dy_sched<SCHED_NT, SCHED_DMAX>; }
 const FwdVariant& fwd_variant(int i) { return g_variants[i]; }
 
 }  // namespace sdnn

@@ -41,6 +41,28 @@ struct LayerArgs {
     int32_t* tile_cnt;           // [max tiles] parts finished per tile
     int32_t parts;               // G: workgroups sharing a tile (each owns NT neurons)
     int32_t nblk;                // 64-neuron blocks
+    // linear (input-gradient) use of the scheduled kernel: weights come from
+    // w[ent_w[...]] and output row p goes to rows_out[p] (or p)
+    const uint32_t* ent_w;
+    const int32_t* rows_out;
+};
+
+// Scheduled weight-gradient pass over one layer (rows are compact 0..R-1).
+struct SchedDwArgs {
+    const float* y_in;           // [R][N] Y_l
+    const float* y_out;          // [R][N] Y_{l+1} (mask)
+    const float* dy;             // [R][N] dL/dY_{l+1}
+    float* g_out;                // [R][N] masked gradient G (written)
+    const int32_t* nrows;        // device R
+    const uint32_t* ent;         // forward schedule of the layer
+    const int32_t* lane_neuron;
+    const int32_t* wave_steps;
+    float* pdw;                  // [S][N][K] per-stream partials
+    float* pdb;                  // [S][N]
+    int32_t N;
+    int32_t parts;
+    int32_t nblk;
+    float clamp;
 };
 
 constexpr int SCHED_T = 4;       // rows per tile of the scheduled kernel
@@ -99,6 +121,8 @@ inline size_t fwd_lds_bytes(const FwdVariant& v, int N) {
 // Host-side slot scheduling (sdnn_sched.hip): see that file.
 int build_schedule(const int32_t* idx, int N, int L, int dmax, uint32_t* ent, int32_t* lane_neuron,
                    int32_t* wave_steps);
+int build_transposed_schedule(const int32_t* idx, int N, int L, int dmax, uint32_t* ent, int32_t* lane_input,
+                              int32_t* wave_steps);
 
 // Small kernels (sdnn_fwd.hip).
 __global__ void k_chain_init(int32_t* cnt, int32_t L, int32_t rows, int32_t compaction, unsigned* bar, int32_t nbar);
@@ -139,6 +163,8 @@ struct BwdDyArgs {
 };
 int bwd_T();
 int bwd_threads();
+const void* bwd_dw_sched_fn();
+const void* bwd_dy_sched_fn();
 const void* bwd_dw_fn();
 const void* bwd_dy_fn();
 __global__ void k_reduce_partials(const float* pdw, const float* pdb, int32_t P, int32_t N, float* dw, float* db);

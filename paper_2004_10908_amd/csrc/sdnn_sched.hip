@@ -111,9 +111,84 @@ void balance(const Block& B, std::array<int, 64>& members_out) {
 
 }  // namespace
 
-// Build the schedule of layers [l0, l1).  idx: host copy of all ids [L][N][K].
-// Output (host):
-//   ent[(l*npad + lane_slot)*dmax + s] = (id << 5) | k, or dummy (bit 31 set, id = free group)
+// One scheduled item: the bank group of the LDS slot a lane reads, and what the
+// caller stores for it.
+struct Item {
+    int group;
+    uint32_t payload;
+};
+
+// Schedule one block of up to 64 lanes; lists[i] are the items of block-local
+// lane i (i < n).  Fills member[wave lane] (block-local index, >= n: none) and
+// seq[wave lane] (payloads, or 0x80000000 | group for padding steps).
+int schedule_block(const std::array<std::vector<Item>, 64>& lists, int n, std::array<int, 64>& member,
+                   std::array<std::vector<uint32_t>, 64>& seq) {
+    Block B;
+    B.n = n;
+    for (int i = 0; i < n; ++i)
+        for (const Item& it : lists[i]) B.hist[i][it.group]++;
+    balance(B, member);
+    std::array<std::array<std::vector<uint32_t>, NG>, 64> pend;
+    std::array<int, 64> left{};
+    for (int lane = 0; lane < 64; ++lane) {
+        seq[lane].clear();
+        const int i = member[lane];
+        if (i >= n) continue;
+        for (const Item& it : lists[i]) {
+            pend[lane][it.group].push_back(it.payload);
+            ++left[lane];
+        }
+    }
+    int steps_blk = 0;
+    for (int u = 0; u < UNITS; ++u) {
+        int lanes[ULANES];
+        for (int q = 0; q < ULANES; ++q) lanes[q] = unit_lane(u, q);
+        int remaining = 0;
+        for (int q = 0; q < ULANES; ++q) remaining += left[lanes[q]];
+        while (remaining > 0) {
+            bool used[NG] = {};
+            int pick[ULANES];
+            int ord[ULANES];
+            for (int q = 0; q < ULANES; ++q) ord[q] = q;
+            std::stable_sort(ord, ord + ULANES, [&](int a, int c) { return left[lanes[a]] > left[lanes[c]]; });
+            for (int oi = 0; oi < ULANES; ++oi) {
+                const int q = ord[oi], lane = lanes[q];
+                pick[q] = -1;
+                int bg = -1, bc = 0;
+                for (int g = 0; g < NG; ++g) {
+                    const int c = (int)pend[lane][g].size();
+                    if (c > bc && !used[g]) { bc = c; bg = g; }
+                }
+                if (bg >= 0) { used[bg] = true; pick[q] = bg; }
+            }
+            for (int q = 0; q < ULANES; ++q) {
+                const int lane = lanes[q];
+                if (pick[q] >= 0) {
+                    seq[lane].push_back(pend[lane][pick[q]].back());
+                    pend[lane][pick[q]].pop_back();
+                    --left[lane];
+                    --remaining;
+                } else {
+                    int g = 0;
+                    while (used[g]) ++g;
+                    used[g] = true;
+                    seq[lane].push_back(0x80000000u | (uint32_t)g);
+                }
+            }
+        }
+        steps_blk = std::max(steps_blk, (int)seq[lanes[0]].size());
+    }
+    // pad to the block's step count: all 16 lanes of a unit take distinct groups
+    for (int u = 0; u < UNITS; ++u)
+        for (int q = 0; q < ULANES; ++q) {
+            auto& sq = seq[unit_lane(u, q)];
+            while ((int)sq.size() < steps_blk) sq.push_back(0x80000000u | (uint32_t)q);
+        }
+    return steps_blk;
+}
+
+// Forward schedule of layers [l0, l1).  idx: host copy of all ids [L][N][K].
+//   ent[(l*npad + lane_slot)*dmax + s] = (id << 5) | k, or padding (bit 31 set, id = free group, k = 31)
 //   lane_neuron[l*npad + lane_slot]   = neuron computed by that lane slot, or -1
 //   wave_steps[l*nblk + b]            = steps of block b
 // Returns the largest step count seen (callers reject > dmax).
@@ -121,103 +196,111 @@ int build_schedule_range(const int32_t* idx, int N, int l0, int l1, int dmax, ui
                          int32_t* wave_steps) {
     const int nblk = (N + 63) / 64, npad = nblk * 64;
     int worst = 0;
+    std::array<std::vector<Item>, 64> lists;
+    std::array<int, 64> member;
+    std::array<std::vector<uint32_t>, 64> seq;
     for (int l = l0; l < l1; ++l) {
         const int32_t* il = idx + (size_t)l * N * K;
         for (int b = 0; b < nblk; ++b) {
-            Block B;
-            B.n = std::min(64, N - 64 * b);
-            for (int i = 0; i < B.n; ++i)
-                for (int k = 0; k < K; ++k) B.hist[i][il[(size_t)(64 * b + i) * K + k] % NG]++;
-            std::array<int, 64> member;   // member[lane] = local neuron index 0..63 (>= n: phantom)
-            balance(B, member);
-            // per lane: list of slots k by group
-            std::array<std::array<std::vector<int>, NG>, 64> pend;
-            std::array<int, 64> left{};
-            for (int lane = 0; lane < 64; ++lane) {
-                const int i = member[lane];
-                if (i >= B.n) continue;
+            const int n = std::min(64, N - 64 * b);
+            for (int i = 0; i < 64; ++i) {
+                lists[i].clear();
+                if (i >= n) continue;
                 for (int k = 0; k < K; ++k) {
-                    pend[lane][il[(size_t)(64 * b + i) * K + k] % NG].push_back(k);
-                    ++left[lane];
+                    const int32_t id = il[(size_t)(64 * b + i) * K + k];
+                    lists[i].push_back({id % NG, ((uint32_t)id << 5) | (uint32_t)k});
                 }
             }
-            // schedule every unit
-            std::array<std::vector<uint32_t>, 64> seq;
-            int steps_blk = 0;
-            for (int u = 0; u < UNITS; ++u) {
-                int lanes[ULANES];
-                for (int q = 0; q < ULANES; ++q) lanes[q] = unit_lane(u, q);
-                int remaining = 0;
-                for (int q = 0; q < ULANES; ++q) remaining += left[lanes[q]];
-                while (remaining > 0) {
-                    bool used[NG] = {};
-                    int pick[ULANES];
-                    int ord[ULANES];
-                    for (int q = 0; q < ULANES; ++q) ord[q] = q;
-                    std::stable_sort(ord, ord + ULANES, [&](int a, int c) { return left[lanes[a]] > left[lanes[c]]; });
-                    for (int oi = 0; oi < ULANES; ++oi) {
-                        const int q = ord[oi], lane = lanes[q];
-                        pick[q] = -1;
-                        int bg = -1, bc = 0;
-                        for (int g = 0; g < NG; ++g) {
-                            const int c = (int)pend[lane][g].size();
-                            if (c > bc && !used[g]) { bc = c; bg = g; }
-                        }
-                        if (bg >= 0) { used[bg] = true; pick[q] = bg; }
-                    }
-                    for (int q = 0; q < ULANES; ++q) {
-                        const int lane = lanes[q];
-                        if (pick[q] >= 0) {
-                            const int g = pick[q];
-                            const int k = pend[lane][g].back();
-                            pend[lane][g].pop_back();
-                            --left[lane];
-                            --remaining;
-                            const int32_t id = il[(size_t)(64 * b + member[lane]) * K + k];
-                            seq[lane].push_back(((uint32_t)id << 5) | (uint32_t)k);
-                        } else {
-                            int g = 0;
-                            while (used[g]) ++g;
-                            used[g] = true;
-                            seq[lane].push_back(0x80000000u | ((uint32_t)g << 5) | 31u);
-                        }
-                    }
-                }
-                steps_blk = std::max(steps_blk, (int)seq[lanes[0]].size());
-            }
-            // pad to the block's step count: all 16 lanes of a unit take distinct groups
-            for (int u = 0; u < UNITS; ++u)
-                for (int q = 0; q < ULANES; ++q) {
-                    auto& s = seq[unit_lane(u, q)];
-                    while ((int)s.size() < steps_blk) s.push_back(0x80000000u | ((uint32_t)q << 5) | 31u);
-                }
-            worst = std::max(worst, steps_blk);
-            wave_steps[(size_t)l * nblk + b] = steps_blk;
+            const int steps = schedule_block(lists, n, member, seq);
+            worst = std::max(worst, steps);
+            wave_steps[(size_t)l * nblk + b] = steps;
             for (int lane = 0; lane < 64; ++lane) {
                 const size_t slot = (size_t)l * npad + 64 * b + lane;
-                lane_neuron[slot] = member[lane] < B.n ? 64 * b + member[lane] : -1;
-                for (int s = 0; s < dmax; ++s)
-                    ent[slot * dmax + s] = s < (int)seq[lane].size() ? seq[lane][s] : (0x80000000u | 31u);
+                lane_neuron[slot] = member[lane] < n ? 64 * b + member[lane] : -1;
+                for (int s = 0; s < dmax; ++s) {
+                    uint32_t e = 0x80000000u | 31u;
+                    if (s < (int)seq[lane].size()) {
+                        e = seq[lane][s];
+                        if (e & 0x80000000u) e = 0x80000000u | ((e & 0xffu) << 5) | 31u;
+                    }
+                    ent[slot * dmax + s] = e;
+                }
             }
         }
     }
     return worst;
 }
 
-int build_schedule(const int32_t* idx, int N, int L, int dmax, uint32_t* ent, int32_t* lane_neuron,
-                   int32_t* wave_steps) {
+// Transposed schedule of layers [l0, l1) (for the input-gradient gather): lane
+// slots are input neurons i, items are the edges (j, k) with idx[j][k] = i, read
+// from the gradient tile at column j (bank group j mod 16).
+//   ent[...] = edge position j*K + k, or padding (bit 31 set, j*K = free group * K)
+int build_transposed_range(const int32_t* idx, int N, int l0, int l1, int dmax, uint32_t* ent, int32_t* lane_input,
+                           int32_t* wave_steps) {
+    const int nblk = (N + 63) / 64, npad = nblk * 64;
+    int worst = 0;
+    std::vector<std::vector<uint32_t>> in_edges(N);
+    std::array<std::vector<Item>, 64> lists;
+    std::array<int, 64> member;
+    std::array<std::vector<uint32_t>, 64> seq;
+    for (int l = l0; l < l1; ++l) {
+        const int32_t* il = idx + (size_t)l * N * K;
+        for (auto& v : in_edges) v.clear();
+        for (int j = 0; j < N; ++j)
+            for (int k = 0; k < K; ++k) in_edges[il[(size_t)j * K + k]].push_back((uint32_t)(j * K + k));
+        for (int b = 0; b < nblk; ++b) {
+            const int n = std::min(64, N - 64 * b);
+            for (int i = 0; i < 64; ++i) {
+                lists[i].clear();
+                if (i >= n) continue;
+                for (uint32_t e : in_edges[64 * b + i]) lists[i].push_back({(int)((e / K) % NG), e});
+            }
+            const int steps = schedule_block(lists, n, member, seq);
+            worst = std::max(worst, steps);
+            wave_steps[(size_t)l * nblk + b] = steps;
+            for (int lane = 0; lane < 64; ++lane) {
+                const size_t slot = (size_t)l * npad + 64 * b + lane;
+                lane_input[slot] = member[lane] < n ? 64 * b + member[lane] : -1;
+                for (int s = 0; s < dmax; ++s) {
+                    uint32_t e = 0x80000000u;
+                    if (s < (int)seq[lane].size()) {
+                        e = seq[lane][s];
+                        if (e & 0x80000000u) e = 0x80000000u | ((e & 0xffu) * K);
+                    }
+                    ent[slot * dmax + s] = e;
+                }
+            }
+        }
+    }
+    return worst;
+}
+
+template <typename F>
+int parallel_layers(int L, F f) {
     unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     nth = std::min<unsigned>(nth, (unsigned)L);
     std::vector<std::thread> th;
     std::vector<int> worst(nth, 0);
     for (unsigned t = 0; t < nth; ++t) {
         const int l0 = (int)((int64_t)L * t / nth), l1 = (int)((int64_t)L * (t + 1) / nth);
-        th.emplace_back([=, &worst] {
-            worst[t] = build_schedule_range(idx, N, l0, l1, dmax, ent, lane_neuron, wave_steps);
-        });
+        th.emplace_back([=, &worst, &f] { worst[t] = f(l0, l1); });
     }
     for (auto& x : th) x.join();
     return *std::max_element(worst.begin(), worst.end());
+}
+
+int build_schedule(const int32_t* idx, int N, int L, int dmax, uint32_t* ent, int32_t* lane_neuron,
+                   int32_t* wave_steps) {
+    return parallel_layers(L, [&](int l0, int l1) {
+        return build_schedule_range(idx, N, l0, l1, dmax, ent, lane_neuron, wave_steps);
+    });
+}
+
+int build_transposed_schedule(const int32_t* idx, int N, int L, int dmax, uint32_t* ent, int32_t* lane_input,
+                              int32_t* wave_steps) {
+    return parallel_layers(L, [&](int l0, int l1) {
+        return build_transposed_range(idx, N, l0, l1, dmax, ent, lane_input, wave_steps);
+    });
 }
 
 }  // namespace sdnn

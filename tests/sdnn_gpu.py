@@ -103,7 +103,7 @@ def check_grad(g_gpu, g_ref, bound, what, normwise=True):
     assert not bad.any(), f"{what}: {int(bad.sum())} elements outside tolerance, worst excess {(np.abs(d) - tol)[bad].max()}"
 
 
-def backward_bounds(layers, ys, eys, dy_last, clamp, rows_groups=64):
+def backward_bounds(layers, ys, eys, dy_last, clamp, rows_groups=256):
     """First-order error bounds of an fp32 backward pass (masks taken as the oracle's).
 
     ys/eys: exact activations and their forward error bounds per layer; dy_last is

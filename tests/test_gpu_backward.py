@@ -33,9 +33,9 @@ def oracle_grads(layers, y0h, dy_h, clamp):
     return ref, dws, dbs, dy0
 
 
-def layer_sync_bounds(idx, w, clamp, y_in, y_out, dy, groups=64):
+def layer_sync_bounds(idx, w, clamp, y_in, y_out, dy, groups=256):
     """Exact fp64 layer backward on the fp32 inputs and the summation-error bounds
-    of an fp32 evaluation: gamma_{R+P} sum|G||Y| (dW), gamma_{R+P} sum|G| (db),
+    of an fp32 evaluation: gamma_{R+P} sum|G||Y| (dW), gamma_{R+P} sum|G| (db) with P <= 256 partials,
     gamma_{deg+1} sum|w||G| (dY)."""
     R = y_in.shape[0]
     dw, db, dyi = oracle.layer_backward(idx, w, clamp, y_in, y_out, dy)
