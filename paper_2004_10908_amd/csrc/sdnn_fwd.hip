@@ -285,7 +285,7 @@ __global__ __launch_bounds__(NT) void k_chain(ChainArgs c) {
         const int R = (l == 0 || !c.compaction) ? c.rows : ld_acquire(&c.cnt[l]);
         if (R == 0) break;
         const bool out_is_y = ((L - 1 - l) & 1) == 0;
-        LayerArgs a;
+        LayerArgs a{};
         a.yin = l == 0 ? c.y0 : (out_is_y ? c.act : c.y_out);
         a.yout = out_is_y ? c.y_out : c.act;
         a.ycopy = (c.ckpt && (l + 1) % c.ckpt_every == 0 && l + 1 < L)
@@ -586,7 +586,7 @@ __global__ __launch_bounds__(NT) void k_chain_sched(ChainArgs c) {
         const int R = (l == 0 || !c.compaction) ? c.rows : ld_acquire(&c.cnt[l]);
         if (R == 0) break;
         const bool out_is_y = ((L - 1 - l) & 1) == 0;
-        LayerArgs a;
+        LayerArgs a{};
         a.yin = l == 0 ? c.y0 : (out_is_y ? c.act : c.y_out);
         a.yout = out_is_y ? c.y_out : c.act;
         a.ycopy = (c.ckpt && (l + 1) % c.ckpt_every == 0 && l + 1 < L)
