@@ -23,7 +23,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 CFLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function",
-          "-Wno-unused-result"]
+          "-Wno-unused-result",
+          # keep single-lane atomics as written: the wave-level atomic combining pass
+          # would wait for each returned value right away
+          "-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]
 
 
 def _compile(src: str) -> str:

@@ -58,7 +58,7 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Layout {
     size_t act = 0, list0 = 0, list1 = 0, alive = 0, cnt = 0, bar = 0, err = 0, flag = 0;
-    size_t ent = 0, lane_neuron = 0, wave_steps = 0, tile_bits = 0, tile_cnt = 0;
+    size_t ent = 0, lane_neuron = 0, wave_steps = 0, tile_bits = 0;
     size_t ent_t = 0, ent_w = 0, lane_input = 0, steps_t = 0, gbuf2 = 0;
     bool sched = false;
     size_t tr_ptr = 0, tr_e = 0, seg = 0, gbuf0 = 0, gbuf1 = 0, pdw = 0, pdb = 0;
@@ -74,7 +74,7 @@ int sched_parts(const sdnn_desc& d) { return ((d.n_neurons + 63) / 64 + 15) / 16
 bool sched_possible(const sdnn_desc& d) {
     const int nblk = (d.n_neurons + 63) / 64;
     const int G = (nblk + 15) / 16;
-    return d.n_neurons % 16 == 0 && (size_t)2 * SCHED_T * d.n_neurons * 4 <= LDS_BUDGET && (G == 1 || G == 2 || G == 4);
+    return d.n_neurons % 16 == 0 && sched_lds_bytes(d.n_neurons) <= LDS_BUDGET && (G == 1 || G == 2 || G == 4);
 }
 
 Layout make_layout(const sdnn_desc& d) {
@@ -98,7 +98,6 @@ Layout make_layout(const sdnn_desc& d) {
         y.lane_neuron = take(L * npad * 4);
         y.wave_steps = take(L * nblk * 4);
         y.tile_bits = take(((R + SCHED_T - 1) / SCHED_T) * 4);
-        y.tile_cnt = take(((R + SCHED_T - 1) / SCHED_T) * 4);
     }
     y.bar = take(NBAR * 4);
     y.err = take(64);
@@ -197,7 +196,7 @@ struct sdnn_net_s {
     bool compaction = true;
     bool sched = false;                 // scheduled kernel available (schedule built)
     uint32_t* ent = nullptr;
-    int32_t *lane_neuron = nullptr, *wave_steps = nullptr, *tile_bits = nullptr, *tile_cnt = nullptr;
+    int32_t *lane_neuron = nullptr, *wave_steps = nullptr, *tile_bits = nullptr;
     int parts = 1, nblk = 0;
     bool sched_bwd = false;             // transposed schedule built (scheduled backward)
     uint32_t *ent_t = nullptr, *ent_w = nullptr;
@@ -233,7 +232,6 @@ void fill_sched(const sdnn_net_s* n, LayerArgs& a, int l) {
     a.lane_neuron = n->lane_neuron + (size_t)l * npad;
     a.wave_steps = n->wave_steps + (size_t)l * n->nblk;
     a.tile_bits = n->tile_bits;
-    a.tile_cnt = n->tile_cnt;
     a.parts = n->parts;
     a.nblk = n->nblk;
 }
@@ -423,7 +421,6 @@ Plan plan_persistent(const sdnn_net_s* n, const float* y0, int64_t rows, float* 
         c.lane_neuron = n->lane_neuron;
         c.wave_steps = n->wave_steps;
         c.tile_bits = n->tile_bits;
-        c.tile_cnt = n->tile_cnt;
         c.parts = n->parts;
         c.nblk = n->nblk;
     }
@@ -485,7 +482,7 @@ sdnn_status backward_layer_sched(const sdnn_net_s* n, int l, const float* y_in, 
         a.nblk = n->nblk;
         a.rows_out = rows_out;
         void* yargs[] = {&a};
-        HIPCHK(hipLaunchKernel(bwd_dy_sched_fn(), dim3(SCHED_GRID), dim3(SCHED_NT), yargs, sh, s));
+        HIPCHK(hipLaunchKernel(bwd_dy_sched_fn(), dim3(SCHED_GRID), dim3(SCHED_NT), yargs, sched_lds_bytes(N), s));
     }
     (void)rows;
     HIPCHK(hipGetLastError());
@@ -620,7 +617,6 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
         n->lane_neuron = (int32_t*)(n->ws + lay.lane_neuron);
         n->wave_steps = (int32_t*)(n->ws + lay.wave_steps);
         n->tile_bits = (int32_t*)(n->ws + lay.tile_bits);
-        n->tile_cnt = (int32_t*)(n->ws + lay.tile_cnt);
         std::vector<int32_t> hidx((size_t)L * N * K);
         HIPCHK(hipMemcpyAsync(hidx.data(), idx, hidx.size() * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -641,7 +637,6 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
                 HIPCHK(hipMemcpyAsync(n->wave_steps, hws.data(), hws.size() * 4, hipMemcpyHostToDevice, s));
                 const int64_t nt = (std::max<int64_t>(desc->max_rows, 1) + SCHED_T - 1) / SCHED_T;
                 hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nt)), dim3(256), 0, s, n->tile_bits, nt, 0);
-                hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nt)), dim3(256), 0, s, n->tile_cnt, nt, 0);
                 HIPCHK(hipGetLastError());
                 HIPCHK(hipStreamSynchronize(s));
                 n->sched = true;
@@ -673,7 +668,8 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
                     HIPCHK(hipStreamSynchronize(s));
                     const size_t sh = (size_t)2 * SCHED_T * N * 4 + 64;
                     HIPCHK(hipFuncSetAttribute(bwd_dw_sched_fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
-                    HIPCHK(hipFuncSetAttribute(bwd_dy_sched_fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+                    HIPCHK(hipFuncSetAttribute(bwd_dy_sched_fn(), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                              (int)sched_lds_bytes(N)));
                     n->sched_bwd = true;
                 }
             }

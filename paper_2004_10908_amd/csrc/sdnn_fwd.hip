@@ -347,58 +347,35 @@ __device__ __forceinline__ float4 lds_read16(uint32_t addr) {
 #endif
 }
 
-template <int DMAX, int BUF>
-__device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_base, const uint32_t (&off)[DMAX],
-                                            const float (&wv)[DMAX], int D, int slot, int j, float (&acc)[SCHED_T]) {
-    // Steps in groups of 4; the reads of group g+1 are issued before the FMAs of
-    // group g (ping-pong register sets).  Steps past D are padding (id 0, weight 0:
-    // a broadcast read), so reading one group ahead is always safe.
-    static_assert(DMAX % 4 == 0, "groups of 4");
-    float4 v[2][4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) v[0][u] = lds_read16(off[u] + BUF * 256);
-#pragma unroll
-    for (int g = 0; g < DMAX / 4; ++g) {
-        if (4 * g < D) {
-            if (g + 1 < DMAX / 4) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) v[(g + 1) & 1][u] = lds_read16(off[4 * (g + 1) + u] + BUF * 256);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int st = 4 * g + u;
-                const float4 c = v[g & 1][u];
-                acc[0] = fmaf(wv[st], c.x, acc[0]);
-                acc[1] = fmaf(wv[st], c.y, acc[1]);
-                acc[2] = fmaf(wv[st], c.z, acc[2]);
-                acc[3] = fmaf(wv[st], c.w, acc[3]);
-            }
-        }
-    }
-    if (D > DMAX) {
-        // rare blocks with a longer schedule: remaining steps come from memory
-        for (int st = DMAX; st < D; ++st) {
-            const uint32_t e = a.ent[(size_t)slot * SCHED_DSTORE + st];
-            const bool pad = (e & 0x80000000u) || j < 0;
-            const float w = pad ? 0.f : (a.ent_w ? a.w[a.ent_w[(size_t)slot * SCHED_DSTORE + st]]
-                                                  : a.w[(size_t)j * K + (e & 31u)]);
-            const float4 c = lds_read16(lds_base + ((e >> 5) & 0x03ffffffu) + BUF * 256);
-            acc[0] = fmaf(w, c.x, acc[0]);
-            acc[1] = fmaf(w, c.y, acc[1]);
-            acc[2] = fmaf(w, c.z, acc[2]);
-            acc[3] = fmaf(w, c.w, acc[3]);
-        }
-    }
+// 8-byte LDS read at an absolute LDS byte address.
+__device__ __forceinline__ uint2 lds_read8(uint32_t addr) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef unsigned v2u __attribute__((ext_vector_type(2)));
+    __builtin_assume((addr & 7u) == 0u);
+    const v2u r = *reinterpret_cast<const v2u __attribute__((address_space(3)))*>(addr);
+    return make_uint2(r.x, r.y);
+#else
+    (void)addr;
+    return make_uint2(0u, 0u);
+#endif
 }
 
 // One lane's resident neuron: schedule offsets and weights of one 64-neuron block.
+// Steps past DMAX (rare long blocks) are kept in LDS as (offset, weight) pairs
+// when the workgroup's overflow area has room, else read from memory.
 template <int DMAX>
 struct SchedNeuron {
     uint32_t off[DMAX];
     float wv[DMAX];
     int D, slot, j;
     float bj;
-    __device__ __forceinline__ void load(const LayerArgs& a, int blk, int lane, uint32_t lds_base) {
+    uint32_t ovf;   // LDS byte address of this block's overflow pairs (64 lanes x 8 bytes per step), or ~0u
+    __device__ __forceinline__ float weight_of(const LayerArgs& a, uint32_t e, int st) const {
+        const bool pad = (e & 0x80000000u) || j < 0;
+        return pad ? 0.f : (a.ent_w ? a.w[a.ent_w[(size_t)slot * SCHED_DSTORE + st]] : a.w[(size_t)j * K + (e & 31u)]);
+    }
+    __device__ __forceinline__ void load(const LayerArgs& a, int first_blk, int blk, int lane, uint32_t lds_base,
+                                         uint32_t ovf_base, float* lds) {
         const bool have = blk < a.nblk;
         slot = blk * 64 + lane;
         j = have ? a.lane_neuron[slot] : -1;
@@ -412,25 +389,107 @@ struct SchedNeuron {
 #pragma unroll
         for (int st = 0; st < DMAX; ++st) {
             off[st] = lds_base + ((e[st] >> 5) & 0x03ffffffu);
-            const bool pad = (e[st] & 0x80000000u) || j < 0;
-            wv[st] = pad ? 0.f : (a.ent_w ? a.w[a.ent_w[(size_t)slot * SCHED_DSTORE + st]]
-                                          : a.w[(size_t)j * K + (e[st] & 31u)]);
+            wv[st] = weight_of(a, e[st], st);
+        }
+        bj = (j >= 0 && a.b) ? a.b[j] : 0.f;
+        ovf = ~0u;
+        if (D > DMAX) {
+            // the part's blocks take the overflow area in block order
+            int pre = 0;
+            for (int b2 = first_blk; b2 < blk; ++b2)
+                pre += max(0, __builtin_amdgcn_readfirstlane(a.wave_steps[b2]) - DMAX);
+            if (pre + (D - DMAX) <= SCHED_OVF) {
+                ovf = ovf_base + (uint32_t)pre * 512u;
+                uint2* dst = reinterpret_cast<uint2*>(reinterpret_cast<char*>(lds) + (ovf - lds_base)) + lane;
+                for (int st = DMAX; st < D; ++st) {
+                    const uint32_t x = a.ent[(size_t)slot * SCHED_DSTORE + st];
+                    dst[(st - DMAX) * 64] =
+                        make_uint2(lds_base + ((x >> 5) & 0x03ffffffu), __float_as_uint(weight_of(a, x, st)));
+                }
+            }
         }
 #pragma unroll
         for (int st = 0; st < DMAX; ++st) __asm__ volatile("" : "+v"(off[st]), "+v"(wv[st]));   // keep resident
-        bj = (j >= 0 && a.b) ? a.b[j] : 0.f;
     }
 };
 
+template <int DMAX, int BUF>
+__device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_base, int lane, const SchedNeuron<DMAX>& n,
+                                            float (&acc)[SCHED_T]) {
+    // Steps in groups of 4; the reads of group g+1 are issued before the FMAs of
+    // group g (ping-pong register sets).  Steps past D are padding (weight 0, a
+    // conflict-free read), so reading one group ahead is always safe.
+    static_assert(DMAX % 4 == 0, "groups of 4");
+    const int D = n.D;
+    float4 v[2][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[0][u] = lds_read16(n.off[u] + BUF * 256);
+#pragma unroll
+    for (int g = 0; g < DMAX / 4; ++g) {
+        if (4 * g < D) {
+            if (g + 1 < DMAX / 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[(g + 1) & 1][u] = lds_read16(n.off[4 * (g + 1) + u] + BUF * 256);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int st = 4 * g + u;
+                const float4 c = v[g & 1][u];
+                acc[0] = fmaf(n.wv[st], c.x, acc[0]);
+                acc[1] = fmaf(n.wv[st], c.y, acc[1]);
+                acc[2] = fmaf(n.wv[st], c.z, acc[2]);
+                acc[3] = fmaf(n.wv[st], c.w, acc[3]);
+            }
+        }
+    }
+    if (D > DMAX) {
+        // the LDS and memory forms are separate loops so that the LDS one never waits
+        // on outstanding memory operations (the staging of the next tile)
+        if (n.ovf != ~0u) {
+            for (int st = DMAX; st < D; ++st) {
+                const uint2 e = lds_read8(n.ovf + (uint32_t)(st - DMAX) * 512u + 8u * (uint32_t)lane);
+                const float w = __uint_as_float(e.y);
+                const float4 c = lds_read16(e.x + BUF * 256);
+                acc[0] = fmaf(w, c.x, acc[0]);
+                acc[1] = fmaf(w, c.y, acc[1]);
+                acc[2] = fmaf(w, c.z, acc[2]);
+                acc[3] = fmaf(w, c.w, acc[3]);
+            }
+        } else {
+            for (int st = DMAX; st < D; ++st) {
+                const uint32_t e = a.ent[(size_t)n.slot * SCHED_DSTORE + st];
+                const float w = n.weight_of(a, e, st);
+                const float4 c = lds_read16(lds_base + ((e >> 5) & 0x03ffffffu) + BUF * 256);
+                acc[0] = fmaf(w, c.x, acc[0]);
+                acc[1] = fmaf(w, c.y, acc[1]);
+                acc[2] = fmaf(w, c.z, acc[2]);
+                acc[3] = fmaf(w, c.w, acc[3]);
+            }
+        }
+    }
+}
+
+// The scheduled layer over R rows (tiles of 4 rows; see the comment above).
+// Per tile each wave: waits for the tile's staging and meets the others at one
+// barrier; stores the previous tile's outputs; issues the staging of the next
+// tile; computes this tile.  No memory load is waited for inside the compute:
+// the row ids of a tile are fetched two tiles ahead, output stores are issued a
+// tile late, and the row-liveness bookkeeping (LINEAR = false, with a work list
+// or alive flags) runs as a pipeline on wave 0: tile t's combined row bits are
+// added to its tile word at tile t+1, the sum is read at tile t+2 (alive flags,
+// zeroing of dead rows, list slot reservation), the list entries are written at
+// tile t+3, and whatever is left drains after the last tile.
 template <int NT, int DMAX, bool LINEAR = false>
 __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __restrict__ lds, int R) {
     constexpr int T = SCHED_T;
     constexpr int WAVES = NT / 64;
     const int N = a.N;
-    // the workgroup's LDS: two interleaved tile buffers (2 * 4 * N floats), then 4 words
-    unsigned* s_bits = reinterpret_cast<unsigned*>(lds + 2 * T * N);   // [2]
-    unsigned& s_final = s_bits[2];
-    int& s_last = reinterpret_cast<int&>(s_bits[3]);
+    // the workgroup's LDS: two interleaved tile buffers (2 * 4 * N floats), 128 bytes
+    // of scalars (row bits [2] at word 0, the grid barrier's flag at word 4, the row
+    // id rings at words 8 and 16), the overflow area
+    unsigned* s_bits = reinterpret_cast<unsigned*>(lds + 2 * T * N);
+    int* s_pin = reinterpret_cast<int*>(s_bits) + 8;      // [2][4] input rows of coming tiles
+    int* s_pout = reinterpret_cast<int*>(s_bits) + 16;    // [2][4] output rows (linear mode)
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -444,126 +503,190 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
     if (q >= ntiles) return;                         // uniform over the workgroup
     // a part is 16 blocks of 64 neurons; wave w owns blocks 2w and 2w + 1 of it
     const uint32_t lds_base = (uint32_t)(uintptr_t)lds;
+    const uint32_t ovf_base = lds_base + (uint32_t)(2 * T * N * 4 + SCHED_SCALARS);
     SchedNeuron<DMAX> n0, n1;
-    n0.load(a, p * 16 + 2 * wave, lane, lds_base);
-    n1.load(a, p * 16 + 2 * wave + 1, lane, lds_base);
-    // staging: chunk c (ids 16c .. 16c+15, 4 rows, 256 bytes) is loaded by wave c % WAVES;
-    // lane l holds row l % 4 of id 16c + l / 4, so a wave's LDS store is 256 contiguous bytes
+    n0.load(a, p * 16, p * 16 + 2 * wave, lane, lds_base, ovf_base, lds);
+    n1.load(a, p * 16, p * 16 + 2 * wave + 1, lane, lds_base, ovf_base, lds);
+    const bool live = !LINEAR && (a.list_out || a.alive);
+    // Staging: chunk c (ids 16c .. 16c+15, 4 rows, 256 bytes) is loaded by wave c % WAVES;
+    // lane l holds row l % 4 of id 16c + l / 4, so a wave's LDS store is 256 contiguous
+    // bytes.  Row ids: with a work list (and in linear mode with an output row map) the
+    // ids of the tile after next are copied by wave 0 into an LDS ring with the same
+    // asynchronous copies, so no register waits on a memory load inside the loop.
     const int nchunks = N / 16;
-    auto row_of = [&](int tile, int t) {
-        const int pos = tile * T + t;
-        const int pp = pos < R ? pos : tile * T;     // padding rows repeat the tile's first row
-        return a.list_in ? a.list_in[pp] : a.row_base + pp;
+    auto pos_of = [&](int tile) -> int {
+        const int pos = tile * T + (lane & 3);
+        return pos < R ? pos : tile * T;             // padding rows repeat the tile's first row
+    };
+    auto copy4 = [&](const int32_t* src, int* ring_slot) {
+        // lanes 0..3 of wave 0: one dword each into ring_slot[lane]
+        const uint32_t dst = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)ring_slot);
+        uint32_t saved;
+        __asm__ volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\tglobal_load_lds_dword %1, off\n\ts_mov_b32 m0, %0"
+                         : "=&s"(saved) : "v"(src), "s"(dst) : "memory");
+    };
+    auto prefetch = [&](int tile, int slot) {
+        if (wave == 0 && lane < T) {
+            const int pp = pos_of(tile);
+            if (a.list_in) copy4(a.list_in + pp, s_pin + 4 * slot);
+            if (LINEAR && a.rows_out) copy4(a.rows_out + pp, s_pout + 4 * slot);
+        }
+    };
+    // rows of a tile whose ids are in ring slot `slot` (valid after the barrier that follows the copy)
+    auto in_row = [&](int tile, int slot) -> int { return a.list_in ? s_pin[4 * slot + (lane & 3)] : a.row_base + pos_of(tile); };
+    auto out_row = [&](int tile, int slot) -> int {
+        return (LINEAR && a.rows_out) ? s_pout[4 * slot + (lane & 3)] : in_row(tile, slot);
     };
     // Asynchronous global->LDS copies (each lane's dword lands at M0 + 4 * lane).
     // Issued from inline asm so the compiler does not make every LDS read wait for
     // them; the wait is explicit: s_waitcnt vmcnt(0) + barrier before a buffer is read.
-    auto stage = [&](int tile, int buf) {
-        const float* src = a.yin + (size_t)row_of(tile, lane & 3) * N + (lane >> 2);
+    auto stage = [&](int row, int buf) {
+        const float* src = a.yin + (size_t)row * N + (lane >> 2) + 16 * wave;
+        uint32_t dst = __builtin_amdgcn_readfirstlane(lds_base + 512u * wave + 256u * buf);
         for (int c = wave; c < nchunks; c += WAVES) {
-            const uint32_t dst = __builtin_amdgcn_readfirstlane(lds_base + 512u * c + 256u * buf);
-            const float* g = src + 16 * c;
             uint32_t saved;
             __asm__ volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\tglobal_load_lds_dword %1, off\n\ts_mov_b32 m0, %0"
-                             : "=&s"(saved) : "v"(g), "s"(dst) : "memory");
+                             : "=&s"(saved) : "v"(src), "s"(dst) : "memory");
+            src += 16 * WAVES;
+            dst += 512u * WAVES;
         }
     };
+    // wave 0's liveness pipeline (see above): A = tile whose word add is in flight,
+    // B = tile whose list slots are being reserved
+    int tA = -1, rowA = 0, tB = -1, rowB = 0;
+    unsigned mineA = 0u, oldA = 0u, maskB = 0u;
+    int baseB = 0;
+    auto step_b = [&]() {
+        if (tB >= 0) {
+            const int base = __builtin_amdgcn_readfirstlane(baseB);
+            if (lane < T && ((maskB >> lane) & 1u)) a.list_out[base + __popc(maskB & ((1u << lane) - 1u))] = rowB;
+            tB = -1;
+        }
+    };
+    auto step_a = [&]() {
+        if (tA >= 0) {
+            const unsigned old = __builtin_amdgcn_readfirstlane(oldA);
+            if ((old >> 16) == (unsigned)(G - 1)) {      // this part completed the tile
+                const unsigned full = (old | (mineA << (4 * p))) & 0xffffu;
+                const int nv = min(T, R - tA * T);
+                const unsigned all = (full | (full >> 4) | (full >> 8) | (full >> 12)) & ((1u << nv) - 1u);
+                if (G > 1 && lane == 0) atomicExch(&a.tile_bits[tA], 0);
+                if (a.alive && lane < nv) a.alive[rowA] = (int32_t)((all >> lane) & 1u);
+                if (a.yzero) {
+#pragma unroll
+                    for (int t = 0; t < T; ++t) {
+                        if (t < nv && !((all >> t) & 1u)) {
+                            const int r = __builtin_amdgcn_readlane(rowA, t);
+                            float4* z = reinterpret_cast<float4*>(a.yzero + (size_t)r * N);
+                            for (int i = lane; i < N / 4; i += 64) z[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+                        }
+                    }
+                }
+                if (a.list_out && all) {
+                    baseB = lane == 0 ? atomicAdd(a.cnt_out, __popc(all)) : 0;
+                    maskB = all;
+                    rowB = rowA;
+                    tB = tA;
+                }
+            }
+            tA = -1;
+        }
+    };
+    auto push_a = [&](int tile, int row, int buf) {
+        mineA = s_bits[buf];
+        if (lane == 0) s_bits[buf] = 0u;
+        oldA = 0u;
+        if (G > 1 && lane == 0) oldA = (unsigned)atomicAdd(&a.tile_bits[tile], (int)((1u << 16) | (mineA << (4 * p))));
+        tA = tile;
+        rowA = row;
+    };
+
     if (tid == 0) { s_bits[0] = 0u; s_bits[1] = 0u; }
-    stage(q, 0);
+    // tile q's ids: plain loads before anything is in flight; tile q + S's: the ring
+    int row_c, orow_c;                               // rows of the tile being computed next
+    {
+        const int pp = pos_of(q);
+        row_c = a.list_in ? a.list_in[pp] : a.row_base + pp;
+        orow_c = (LINEAR && a.rows_out) ? a.rows_out[pp] : row_c;
+    }
+    stage(row_c, 0);
+    if (q + S < ntiles) prefetch(q + S, 1);
+    float o0[T] = {0.f, 0.f, 0.f, 0.f}, o1[T] = {0.f, 0.f, 0.f, 0.f};
+    int tile_p = -1, row_p = 0, orow_p = 0;          // the previous tile (outputs not yet stored)
+    auto store_prev = [&]() {
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            if (tile_p * T + t < R) {
+                const int ro = __builtin_amdgcn_readlane(LINEAR ? orow_p : row_p, t);
+                const size_t base = (size_t)ro * N;
+                if (n0.j >= 0) {
+                    a.yout[base + n0.j] = o0[t];
+                    if (a.ycopy) a.ycopy[base + n0.j] = o0[t];
+                }
+                if (n1.j >= 0) {
+                    a.yout[base + n1.j] = o1[t];
+                    if (a.ycopy) a.ycopy[base + n1.j] = o1[t];
+                }
+            }
+        }
+    };
     int it = 0;
     for (int tile = q; tile < ntiles; tile += S, ++it) {
         const int buf = it & 1;
         __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
         __syncthreads();
-        const bool more = tile + S < ntiles;
-        if (more) stage(tile + S, buf ^ 1);
-        if (tid == 0) s_bits[buf ^ 1] = 0u;
+        if (tile_p >= 0) {
+            store_prev();
+            if (live && wave == 0) {
+                step_b();
+                step_a();
+                push_a(tile_p, row_p, buf ^ 1);
+            }
+        }
+        const int row_now = row_c, orow_now = orow_c;
+        if (tile + S < ntiles) {
+            // ring slot (it + 1) & 1 holds tile + S's ids (copied a tile ago, waited above)
+            row_c = in_row(tile + S, buf ^ 1);
+            orow_c = out_row(tile + S, buf ^ 1);
+            stage(row_c, buf ^ 1);
+        }
+        if (tile + 2 * S < ntiles) prefetch(tile + 2 * S, buf);
         float acc0[T] = {0.f, 0.f, 0.f, 0.f}, acc1[T] = {0.f, 0.f, 0.f, 0.f};
         if (buf == 0) {
-            sched_steps<DMAX, 0>(a, lds_base, n0.off, n0.wv, n0.D, n0.slot, n0.j, acc0);
-            sched_steps<DMAX, 0>(a, lds_base, n1.off, n1.wv, n1.D, n1.slot, n1.j, acc1);
+            sched_steps<DMAX, 0>(a, lds_base, lane, n0, acc0);
+            sched_steps<DMAX, 0>(a, lds_base, lane, n1, acc1);
         } else {
-            sched_steps<DMAX, 1>(a, lds_base, n0.off, n0.wv, n0.D, n0.slot, n0.j, acc0);
-            sched_steps<DMAX, 1>(a, lds_base, n1.off, n1.wv, n1.D, n1.slot, n1.j, acc1);
-        }
-        int rr[T];
-        bool vr[T];
-#pragma unroll
-        for (int t = 0; t < T; ++t) {
-            vr[t] = tile * T + t < R;
-            rr[t] = row_of(tile, t);
+            sched_steps<DMAX, 1>(a, lds_base, lane, n0, acc0);
+            sched_steps<DMAX, 1>(a, lds_base, lane, n1, acc1);
         }
         unsigned bits = 0u;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int j = h ? n1.j : n0.j;
-            const float bj = h ? n1.bj : n0.bj;
-            if (j < 0) continue;
-#pragma unroll
-            for (int t = 0; t < T; ++t) {
-                const float y = LINEAR ? (h ? acc1[t] : acc0[t])
-                                       : fminf(fmaxf((h ? acc1[t] : acc0[t]) + bj, 0.f), a.clamp);
-                if (vr[t]) {
-                    const int ro = LINEAR && a.rows_out ? a.rows_out[tile * T + t] : rr[t];
-                    const size_t o = (size_t)ro * N + j;
-                    a.yout[o] = y;
-                    if (a.ycopy) a.ycopy[o] = y;
-                    bits |= (y != 0.f ? 1u : 0u) << t;
-                }
-            }
+        for (int t = 0; t < T; ++t) {
+            o0[t] = LINEAR ? acc0[t] : fminf(fmaxf(acc0[t] + n0.bj, 0.f), a.clamp);
+            o1[t] = LINEAR ? acc1[t] : fminf(fmaxf(acc1[t] + n1.bj, 0.f), a.clamp);
+            bits |= ((o0[t] != 0.f && n0.j >= 0) || (o1[t] != 0.f && n1.j >= 0)) ? (1u << t) : 0u;
         }
-        if (!LINEAR && (a.list_out || a.alive)) {
+        if (live) {
+            // row liveness: this workgroup's waves meet in LDS (read by wave 0 after the next barrier)
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o);
             if (lane == 0 && bits) atomicOr(&s_bits[buf], bits);
-            __syncthreads();
-            if (tid == 0) {
-                unsigned all = s_bits[buf];
-                int last = 1;
-                if (G > 1) {
-                    atomicOr(&a.tile_bits[tile], (int)all);
-                    __threadfence();
-                    last = atomicAdd(&a.tile_cnt[tile], 1) == G - 1;
-                    if (last) {
-                        __threadfence();
-                        all = (unsigned)atomicOr(&a.tile_bits[tile], 0);
-                        atomicExch(&a.tile_bits[tile], 0);
-                        atomicExch(&a.tile_cnt[tile], 0);
-                    }
-                }
-                if (last && a.list_out) {
-                    int n = 0;
-#pragma unroll
-                    for (int t = 0; t < T; ++t) n += (vr[t] && ((all >> t) & 1u)) ? 1 : 0;
-                    if (n) {
-                        int base = atomicAdd(a.cnt_out, n);
-#pragma unroll
-                        for (int t = 0; t < T; ++t)
-                            if (vr[t] && ((all >> t) & 1u)) a.list_out[base++] = rr[t];
-                    }
-                }
-                s_final = all;
-                s_last = last;
-            }
-            __syncthreads();
-            if (s_last) {
-                const unsigned all = s_final;
-                if (a.alive && tid < T) {
-#pragma unroll
-                    for (int t = 0; t < T; ++t)
-                        if (t == tid && vr[t]) a.alive[rr[t]] = (int32_t)((all >> t) & 1u);
-                }
-                if (a.yzero) {
-#pragma unroll
-                    for (int t = 0; t < T; ++t) {
-                        if (vr[t] && !((all >> t) & 1u)) {
-                            float* z = a.yzero + (size_t)rr[t] * N;
-                            for (int i = tid; i < N; i += NT) z[i] = 0.f;
-                        }
-                    }
-                }
-            }
         }
+        tile_p = tile;
+        row_p = row_now;
+        orow_p = orow_now;
+    }
+    // drain: the last tile's outputs and the rest of the liveness pipeline
+    __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
+    __syncthreads();
+    store_prev();
+    if (live && wave == 0) {
+        step_b();
+        step_a();
+        push_a(tile_p, row_p, (it - 1) & 1);
+        step_b();
+        step_a();
+        step_b();
     }
     __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
 }
@@ -610,7 +733,6 @@ __global__ __launch_bounds__(NT) void k_chain_sched(ChainArgs c) {
         a.lane_neuron = c.lane_neuron + (size_t)l * npad;
         a.wave_steps = c.wave_steps + (size_t)l * c.nblk;
         a.tile_bits = c.tile_bits;
-        a.tile_cnt = c.tile_cnt;
         a.parts = c.parts;
         a.nblk = c.nblk;
         run_layer_sched<NT, DMAX>(a, lds, R);

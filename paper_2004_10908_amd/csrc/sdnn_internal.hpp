@@ -37,8 +37,7 @@ struct LayerArgs {
     const uint32_t* ent;         // [npad][SCHED_DSTORE] slot schedule of this layer
     const int32_t* lane_neuron;  // [npad] neuron of each lane slot (-1: none)
     const int32_t* wave_steps;   // [nblk] steps of each 64-neuron block
-    int32_t* tile_bits;          // [max tiles] row bits combined across neuron parts
-    int32_t* tile_cnt;           // [max tiles] parts finished per tile
+    int32_t* tile_bits;          // [max tiles] (parts done << 16) | per-part row bits, zero between layers
     int32_t parts;               // G: workgroups sharing a tile (each owns NT neurons)
     int32_t nblk;                // 64-neuron blocks
     // linear (input-gradient) use of the scheduled kernel: weights come from
@@ -68,7 +67,16 @@ struct SchedDwArgs {
 constexpr int SCHED_T = 4;       // rows per tile of the scheduled kernel
 constexpr int SCHED_NT = 512;    // its workgroup size (each lane owns two neurons)
 constexpr int SCHED_DMAX = 40;   // schedule steps held in registers
-constexpr int SCHED_DSTORE = 64; // schedule steps stored per lane (steps past SCHED_DMAX are read from memory)
+constexpr int SCHED_DSTORE = 64; // schedule steps stored per lane
+constexpr int SCHED_OVF = 40;    // block-steps past SCHED_DMAX a workgroup keeps in LDS (512 bytes each)
+
+constexpr int SCHED_SCALARS = 128; // bytes of per-workgroup scalars after the tile buffers
+
+// LDS of the scheduled forward kernel: two 4-row tile buffers, the scalars, the
+// overflow area.
+inline size_t sched_lds_bytes(int N) {
+    return (size_t)2 * SCHED_T * N * sizeof(float) + SCHED_SCALARS + (size_t)SCHED_OVF * 512;
+}
 
 // Whole forward pass run by the persistent kernel (all layers, one launch).
 struct ChainArgs {
@@ -96,7 +104,6 @@ struct ChainArgs {
     const int32_t* lane_neuron;  // [L][npad]
     const int32_t* wave_steps;   // [L][nblk]
     int32_t* tile_bits;
-    int32_t* tile_cnt;
     int32_t parts;
     int32_t nblk;
 };
@@ -115,7 +122,7 @@ struct FwdVariant {
 int fwd_variant_count();
 const FwdVariant& fwd_variant(int i);
 inline size_t fwd_lds_bytes(const FwdVariant& v, int N) {
-    return v.staged == 2 ? (size_t)2 * SCHED_T * N * sizeof(float) + 64 : (v.staged ? (size_t)v.T * N * sizeof(float) : 0);
+    return v.staged == 2 ? sched_lds_bytes(N) : (v.staged ? (size_t)v.T * N * sizeof(float) : 0);
 }
 
 // Host-side slot scheduling (sdnn_sched.hip): see that file.
