@@ -3,12 +3,14 @@
 // The scheduled kernel stages 4 activation rows per tile in LDS, [id][row], so
 // the 4 values one input id feeds are one 16-byte slot whose bank group is
 // id mod 16.
-// On gfx950 a 16-byte LDS read is served 16 lanes per cycle, in the lane units
-// {0-7, 24-31}, {8-15, 16-23}, {32-39, 56-63}, {40-47, 48-55}, against 64
-// banks: a unit's read is conflict-free iff its 16 lanes hit 16 distinct bank
-// groups (slot mod 16).  (Measured on the device: 16-byte reads whose units cover
-// all 16 groups run at the contiguous rate; any other grouping, or random ids,
-// runs 2-3x slower.)
+// On gfx950 a 16-byte LDS read is served 16 lanes per cycle against 64 banks,
+// in four fixed lane units made of lane quads: unit 2h + p holds the quads
+// (lanes 4c .. 4c+3) of half-wave h whose index c = 0..7 within the half has bit
+// parity p, e.g. unit 0 = {0-3, 12-15, 20-23, 24-27}.  A unit's read is
+// conflict-free iff its 16 lanes hit 16 distinct bank groups (slot mod 16).
+// (Measured on the device with the LDS bank-conflict counter: exchanging the bank
+// groups of two lanes of a conflict-free pattern stays conflict-free exactly when
+// both lanes are in the same unit.)
 //
 // Each lane owns one neuron for a whole layer and may process its 32 slots in
 // any order.  For every block of 64 neurons (one wave) this file:
@@ -42,8 +44,8 @@ constexpr int ULANES = 16;    // lanes per unit
 
 // wave lane of position q (0..15) in unit u
 inline int unit_lane(int u, int q) {
-    static const int base[UNITS][2] = {{0, 24}, {8, 16}, {32, 56}, {40, 48}};
-    return base[u][q / 8] + (q % 8);
+    static const int quads[2][4] = {{0, 3, 5, 6}, {1, 2, 4, 7}};   // quads of a half-wave by bit parity
+    return 32 * (u / 2) + 4 * quads[u % 2][q / 4] + (q % 4);
 }
 
 struct Block {
