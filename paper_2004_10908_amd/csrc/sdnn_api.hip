@@ -444,7 +444,7 @@ sdnn_status backward_layer_sched(const sdnn_net_s* n, int l, const float* y_in, 
                                  float* db_l, hipStream_t s) {
     const int N = n->d.n_neurons;
     const size_t npad = (size_t)n->nblk * 64;
-    const size_t sh = (size_t)2 * SCHED_T * N * 4 + 64;
+    const size_t sh = (size_t)2 * SCHED_T * N * 4 + SCHED_SCALARS;
     const int S = SCHED_GRID / n->parts;
     SchedDwArgs da{};
     da.y_in = y_in;
@@ -627,10 +627,10 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
             std::vector<int32_t> hln((size_t)L * npad), hws((size_t)L * n->nblk);
             const int worst = build_schedule(hidx.data(), N, L, SCHED_DSTORE, hent.data(), hln.data(), hws.data());
             if (worst <= SCHED_DSTORE) {
-                // the kernel wants LDS byte offsets: id -> 512 (id / 16) + 16 (id % 16)
+                // the kernel wants byte offsets in the [id][row] compute tile: id -> 16 id
                 for (auto& e : hent) {
                     const uint32_t id = (e >> 5) & 0x03ffffffu;
-                    e = (e & 0x8000001fu) | ((((id >> 4) << 9) | ((id & 15u) << 4)) << 5);
+                    e = (e & 0x8000001fu) | ((id << 4) << 5);
                 }
                 HIPCHK(hipMemcpyAsync(n->ent, hent.data(), hent.size() * 4, hipMemcpyHostToDevice, s));
                 HIPCHK(hipMemcpyAsync(n->lane_neuron, hln.data(), hln.size() * 4, hipMemcpyHostToDevice, s));
@@ -654,7 +654,7 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
                         const uint32_t e = tent[i] & 0x7fffffffu;
                         const uint32_t col = e / K;
                         tw[i] = e;
-                        tent[i] = (tent[i] & 0x80000000u) | ((((col >> 4) << 9) | ((col & 15u) << 4)) << 5);
+                        tent[i] = (tent[i] & 0x80000000u) | ((col << 4) << 5);
                     }
                     n->ent_t = (uint32_t*)(n->ws + lay.ent_t);
                     n->ent_w = (uint32_t*)(n->ws + lay.ent_w);
@@ -666,7 +666,7 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
                     HIPCHK(hipMemcpyAsync(n->lane_input, tln.data(), tln.size() * 4, hipMemcpyHostToDevice, s));
                     HIPCHK(hipMemcpyAsync(n->steps_t, tws.data(), tws.size() * 4, hipMemcpyHostToDevice, s));
                     HIPCHK(hipStreamSynchronize(s));
-                    const size_t sh = (size_t)2 * SCHED_T * N * 4 + 64;
+                    const size_t sh = (size_t)2 * SCHED_T * N * 4 + SCHED_SCALARS;
                     HIPCHK(hipFuncSetAttribute(bwd_dw_sched_fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
                     HIPCHK(hipFuncSetAttribute(bwd_dy_sched_fn(), hipFuncAttributeMaxDynamicSharedMemorySize,
                                               (int)sched_lds_bytes(N)));

@@ -312,26 +312,84 @@ __global__ __launch_bounds__(NT) void k_chain(ChainArgs c) {
 }
 
 // ---------------------------------------------------------------- scheduled kernel
-// Resident-weight variant for rows that fit LDS twice at 4 rows per tile
-// (N <= 4096).  A workgroup of 1024 lanes owns 1024 neurons ("part") for the
-// whole layer: each lane keeps its neuron's slot schedule (LDS byte offsets) and
-// weights in registers, so the weights are read once per layer per workgroup
-// instead of once per tile.  Tiles of 4 rows are staged into one of two LDS
-// buffers with asynchronous global->LDS loads while the other buffer is being
-// consumed.  The slot order comes from the create-time scheduler, so every
-// 16-byte LDS read of a lane unit hits 16 distinct bank groups.  With G parts
-// per layer (G = ceil(N / 1024)), the G workgroups that share a tile combine
-// their row bits with device atomics; the last one to finish the tile appends
-// the alive rows, writes the alive flags and zeroes dead rows where needed.
-// Workgroup b serves part (b/8) % G of tile stream (b/(8G))*8 + b%8, so the parts
-// of a tile run on the same XCD (blockIdx % 8) and share its L2.
-// LDS layout: the two tile buffers are interleaved in 256-byte blocks, block m of
-// buffer b at byte (2m + b) * 256; ids 16m .. 16m+15 of a 4-row tile fill block m
-// ([id][row], 16 bytes per id).  An id's byte offset in buffer 0 is
-// 512 (id / 16) + 16 (id % 16); buffer 1 is the same plus an immediate 256, so the
-// per-step offset registers serve both buffers and the bank group (16-byte slot
-// mod 16) is id mod 16 in either.
-__device__ __forceinline__ uint32_t sched_off(uint32_t id) { return ((id >> 4) << 9) | ((id & 15u) << 4); }
+// Resident-weight variant for layers whose 4-row tile fits LDS twice
+// (N <= 4096 or so).  A workgroup of 512 lanes owns 1024 neurons ("part") for the
+// whole layer: each lane keeps the slot schedule (LDS byte offsets) and weights
+// of two neurons in registers, so the weights are read once per layer per
+// workgroup instead of once per tile.  The slot order comes from the create-time
+// scheduler, so every 16-byte LDS read of a lane unit hits 16 distinct bank
+// groups.  With G parts per layer (G = ceil(N / 1024)), the G workgroups that
+// share a tile combine their row bits with one device atomic each; the last one
+// to finish the tile appends the alive rows, writes the alive flags and zeroes
+// dead rows where needed.  Workgroup b serves part (b/8) % G of tile stream
+// (b/(8G))*8 + b%8, so the parts of a tile run on the same XCD (blockIdx % 8)
+// and share its L2.
+//
+// LDS: the compute tile C, [id][row] (16 bytes per id, the 4 rows of one input:
+// one 16-byte read feeds 4 FMAs, and id's bank group is id mod 16), then the
+// landing area A, row-major (4 rows of N floats), then 128 bytes of scalars,
+// then the overflow area.  The rows of the next tile arrive in A with
+// asynchronous 16-byte-per-lane global->LDS copies (1 KB of one row per
+// instruction) while C is being read; at the top of a tile the workgroup
+// transposes A into C.
+struct SchedLds {
+    float* C;             // [N][4]
+    float* A;             // [4][N]
+    unsigned* scalars;    // 32 words
+    uint32_t base;        // LDS byte address of C
+    uint32_t land;        // LDS byte address of A
+    uint32_t ovf;         // LDS byte address of the overflow area
+    int N;
+    __device__ __forceinline__ SchedLds(float* lds, int n)
+        : C(lds), A(lds + 4 * n), scalars(reinterpret_cast<unsigned*>(lds + 8 * n)),
+          base((uint32_t)(uintptr_t)lds), land((uint32_t)(uintptr_t)lds + 16u * n),
+          ovf((uint32_t)(uintptr_t)lds + 32u * n + SCHED_SCALARS), N(n) {}
+    // Issue the copies of 4 rows of src into A; row t's id is in lane t of `row`.
+    // 1 KB pieces (256 floats of one row), wave w issuing pieces w, w + waves, ...
+    __device__ __forceinline__ void stage(const float* src, int row, int wave, int lane, int waves) const {
+        const int P = (N + 255) >> 8;
+        for (int c = wave; c < SCHED_T * P; c += waves) {
+            const int r = c / P;
+            const int col = 256 * (c - r * P);
+            const int rid = __builtin_amdgcn_readlane(row, r);
+            const int n = col + 4 * lane;
+            if (n < N) {
+                const float* g = src + (size_t)rid * N + n;
+                const uint32_t dst = __builtin_amdgcn_readfirstlane(land + 4u * (uint32_t)(r * N + col));
+                uint32_t saved;
+                __asm__ volatile(
+                    "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %1, off\n\ts_mov_b32 m0, %0"
+                    : "=&s"(saved) : "v"(g), "s"(dst) : "memory");
+            }
+        }
+    }
+    // A (row-major) -> C ([id][row]); the caller brackets it with barriers.  Eight ids
+    // per thread per round, all reads issued before the writes.
+    __device__ __forceinline__ void transpose(int tid, int nt) const {
+        for (int i0 = tid; i0 < N; i0 += 8 * nt) {
+            float4 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + u * nt;
+                if (i < N) v[u] = make_float4(A[i], A[N + i], A[2 * N + i], A[3 * N + i]);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + u * nt;
+                if (i < N) reinterpret_cast<float4*>(C)[i] = v[u];
+            }
+        }
+    }
+};
+
+// Lanes 0..3 of a wave: one dword each from src[lane] into dst[lane] (an LDS
+// pointer), asynchronously; waited for with the tile's copies.
+__device__ __forceinline__ void lds_copy4(const int32_t* src, int* dst_lds) {
+    const uint32_t dst = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)dst_lds);
+    uint32_t saved;
+    __asm__ volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\tglobal_load_lds_dword %1, off\n\ts_mov_b32 m0, %0"
+                     : "=&s"(saved) : "v"(src), "s"(dst) : "memory");
+}
 
 // 16-byte LDS read at an absolute LDS byte address (the offsets already include
 // the workgroup's LDS base), so the address register is used as is.
@@ -380,7 +438,7 @@ struct SchedNeuron {
         slot = blk * 64 + lane;
         j = have ? a.lane_neuron[slot] : -1;
         D = have ? __builtin_amdgcn_readfirstlane(a.wave_steps[blk]) : 0;
-        // entries hold the LDS byte offset of the slot's id (see sched_off) and the slot;
+        // entries hold the byte offset of the slot's id in the compute tile (16 id) and the slot;
         // all loads are issued before any is waited for
         uint32_t e[DMAX];
 #pragma unroll
@@ -413,7 +471,7 @@ struct SchedNeuron {
     }
 };
 
-template <int DMAX, int BUF>
+template <int DMAX>
 __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_base, int lane, const SchedNeuron<DMAX>& n,
                                             float (&acc)[SCHED_T]) {
     // Steps in groups of 4; the reads of group g+1 are issued before the FMAs of
@@ -423,13 +481,13 @@ __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_bas
     const int D = n.D;
     float4 v[2][4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[0][u] = lds_read16(n.off[u] + BUF * 256);
+    for (int u = 0; u < 4; ++u) v[0][u] = lds_read16(n.off[u]);
 #pragma unroll
     for (int g = 0; g < DMAX / 4; ++g) {
         if (4 * g < D) {
             if (g + 1 < DMAX / 4) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) v[(g + 1) & 1][u] = lds_read16(n.off[4 * (g + 1) + u] + BUF * 256);
+                for (int u = 0; u < 4; ++u) v[(g + 1) & 1][u] = lds_read16(n.off[4 * (g + 1) + u]);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -449,7 +507,7 @@ __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_bas
             for (int st = DMAX; st < D; ++st) {
                 const uint2 e = lds_read8(n.ovf + (uint32_t)(st - DMAX) * 512u + 8u * (uint32_t)lane);
                 const float w = __uint_as_float(e.y);
-                const float4 c = lds_read16(e.x + BUF * 256);
+                const float4 c = lds_read16(e.x);
                 acc[0] = fmaf(w, c.x, acc[0]);
                 acc[1] = fmaf(w, c.y, acc[1]);
                 acc[2] = fmaf(w, c.z, acc[2]);
@@ -459,7 +517,7 @@ __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_bas
             for (int st = DMAX; st < D; ++st) {
                 const uint32_t e = a.ent[(size_t)n.slot * SCHED_DSTORE + st];
                 const float w = n.weight_of(a, e, st);
-                const float4 c = lds_read16(lds_base + ((e >> 5) & 0x03ffffffu) + BUF * 256);
+                const float4 c = lds_read16(lds_base + ((e >> 5) & 0x03ffffffu));
                 acc[0] = fmaf(w, c.x, acc[0]);
                 acc[1] = fmaf(w, c.y, acc[1]);
                 acc[2] = fmaf(w, c.z, acc[2]);
@@ -470,26 +528,25 @@ __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_bas
 }
 
 // The scheduled layer over R rows (tiles of 4 rows; see the comment above).
-// Per tile each wave: waits for the tile's staging and meets the others at one
-// barrier; stores the previous tile's outputs; issues the staging of the next
-// tile; computes this tile.  No memory load is waited for inside the compute:
-// the row ids of a tile are fetched two tiles ahead, output stores are issued a
-// tile late, and the row-liveness bookkeeping (LINEAR = false, with a work list
-// or alive flags) runs as a pipeline on wave 0: tile t's combined row bits are
-// added to its tile word at tile t+1, the sum is read at tile t+2 (alive flags,
-// zeroing of dead rows, list slot reservation), the list entries are written at
-// tile t+3, and whatever is left drains after the last tile.
+// Per tile: wait for the tile's copies and meet at a barrier; store the previous
+// tile's outputs and advance the liveness pipeline; transpose the landed rows
+// into the compute tile; meet again; issue the copies of the next tile; compute.
+// No memory load is waited for inside the compute: the row ids of a tile are
+// fetched two tiles ahead, output stores are issued a tile late, and the row
+// liveness (LINEAR = false, with a work list or alive flags) runs as a pipeline
+// on wave 0: tile t's combined row bits are added to its tile word at tile t+1,
+// the sum is read at tile t+2 (alive flags, zeroing of dead rows, list slot
+// reservation), the list entries are written at tile t+3, and whatever is left
+// drains after the last tile.
 template <int NT, int DMAX, bool LINEAR = false>
 __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __restrict__ lds, int R) {
     constexpr int T = SCHED_T;
     constexpr int WAVES = NT / 64;
     const int N = a.N;
-    // the workgroup's LDS: two interleaved tile buffers (2 * 4 * N floats), 128 bytes
-    // of scalars (row bits [2] at word 0, the grid barrier's flag at word 4, the row
-    // id rings at words 8 and 16), the overflow area
-    unsigned* s_bits = reinterpret_cast<unsigned*>(lds + 2 * T * N);
-    int* s_pin = reinterpret_cast<int*>(s_bits) + 8;      // [2][4] input rows of coming tiles
-    int* s_pout = reinterpret_cast<int*>(s_bits) + 16;    // [2][4] output rows (linear mode)
+    const SchedLds L(lds, N);
+    unsigned* s_bits = L.scalars;                         // [2] row bits of the last two tiles
+    int* s_pin = reinterpret_cast<int*>(L.scalars) + 8;   // [2][4] input rows of coming tiles
+    int* s_pout = reinterpret_cast<int*>(L.scalars) + 16; // [2][4] output rows (linear mode)
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -502,34 +559,23 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
     const int ntiles = (R + T - 1) / T;
     if (q >= ntiles) return;                         // uniform over the workgroup
     // a part is 16 blocks of 64 neurons; wave w owns blocks 2w and 2w + 1 of it
-    const uint32_t lds_base = (uint32_t)(uintptr_t)lds;
-    const uint32_t ovf_base = lds_base + (uint32_t)(2 * T * N * 4 + SCHED_SCALARS);
     SchedNeuron<DMAX> n0, n1;
-    n0.load(a, p * 16, p * 16 + 2 * wave, lane, lds_base, ovf_base, lds);
-    n1.load(a, p * 16, p * 16 + 2 * wave + 1, lane, lds_base, ovf_base, lds);
+    n0.load(a, p * 16, p * 16 + 2 * wave, lane, L.base, L.ovf, lds);
+    n1.load(a, p * 16, p * 16 + 2 * wave + 1, lane, L.base, L.ovf, lds);
     const bool live = !LINEAR && (a.list_out || a.alive);
-    // Staging: chunk c (ids 16c .. 16c+15, 4 rows, 256 bytes) is loaded by wave c % WAVES;
-    // lane l holds row l % 4 of id 16c + l / 4, so a wave's LDS store is 256 contiguous
-    // bytes.  Row ids: with a work list (and in linear mode with an output row map) the
-    // ids of the tile after next are copied by wave 0 into an LDS ring with the same
-    // asynchronous copies, so no register waits on a memory load inside the loop.
-    const int nchunks = N / 16;
+    // Row ids: lane l carries the id of tile row l % 4.  With a work list (and in linear
+    // mode with an output row map) the ids of the tile after next are copied by wave 0
+    // into an LDS ring with asynchronous copies, so no register waits on a memory load
+    // inside the loop.
     auto pos_of = [&](int tile) -> int {
         const int pos = tile * T + (lane & 3);
         return pos < R ? pos : tile * T;             // padding rows repeat the tile's first row
     };
-    auto copy4 = [&](const int32_t* src, int* ring_slot) {
-        // lanes 0..3 of wave 0: one dword each into ring_slot[lane]
-        const uint32_t dst = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)ring_slot);
-        uint32_t saved;
-        __asm__ volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\tglobal_load_lds_dword %1, off\n\ts_mov_b32 m0, %0"
-                         : "=&s"(saved) : "v"(src), "s"(dst) : "memory");
-    };
     auto prefetch = [&](int tile, int slot) {
         if (wave == 0 && lane < T) {
             const int pp = pos_of(tile);
-            if (a.list_in) copy4(a.list_in + pp, s_pin + 4 * slot);
-            if (LINEAR && a.rows_out) copy4(a.rows_out + pp, s_pout + 4 * slot);
+            if (a.list_in) lds_copy4(a.list_in + pp, s_pin + 4 * slot);
+            if (LINEAR && a.rows_out) lds_copy4(a.rows_out + pp, s_pout + 4 * slot);
         }
     };
     // rows of a tile whose ids are in ring slot `slot` (valid after the barrier that follows the copy)
@@ -537,51 +583,29 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
     auto out_row = [&](int tile, int slot) -> int {
         return (LINEAR && a.rows_out) ? s_pout[4 * slot + (lane & 3)] : in_row(tile, slot);
     };
-    // Asynchronous global->LDS copies (each lane's dword lands at M0 + 4 * lane).
-    // Issued from inline asm so the compiler does not make every LDS read wait for
-    // them; the wait is explicit: s_waitcnt vmcnt(0) + barrier before a buffer is read.
-    auto stage = [&](int row, int buf) {
-        const float* src = a.yin + (size_t)row * N + (lane >> 2) + 16 * wave;
-        uint32_t dst = __builtin_amdgcn_readfirstlane(lds_base + 512u * wave + 256u * buf);
-        for (int c = wave; c < nchunks; c += WAVES) {
-            uint32_t saved;
-            __asm__ volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\tglobal_load_lds_dword %1, off\n\ts_mov_b32 m0, %0"
-                             : "=&s"(saved) : "v"(src), "s"(dst) : "memory");
-            src += 16 * WAVES;
-            dst += 512u * WAVES;
-        }
-    };
     // wave 0's liveness pipeline (see above): A = tile whose word add is in flight,
-    // B = tile whose list slots are being reserved
+    // B = tile whose list slots are being reserved.  The returned values are read
+    // first, unconditionally, while nothing else is outstanding; only then are new
+    // stores and atomics issued.
     int tA = -1, rowA = 0, tB = -1, rowB = 0;
     unsigned mineA = 0u, oldA = 0u, maskB = 0u;
     int baseB = 0;
-    auto step_b = [&]() {
+    auto advance = [&](int tile_new, int row_new, unsigned mine_new) {
+        const unsigned old = __builtin_amdgcn_readfirstlane(oldA);
+        const int base = __builtin_amdgcn_readfirstlane(baseB);
+        // B: write the list entries of the tile whose slots were reserved
         if (tB >= 0) {
-            const int base = __builtin_amdgcn_readfirstlane(baseB);
             if (lane < T && ((maskB >> lane) & 1u)) a.list_out[base + __popc(maskB & ((1u << lane) - 1u))] = rowB;
             tB = -1;
         }
-    };
-    auto step_a = [&]() {
+        // A: the word sum is back; the part that completed the tile publishes it
         if (tA >= 0) {
-            const unsigned old = __builtin_amdgcn_readfirstlane(oldA);
-            if ((old >> 16) == (unsigned)(G - 1)) {      // this part completed the tile
+            if ((old >> 16) == (unsigned)(G - 1)) {
                 const unsigned full = (old | (mineA << (4 * p))) & 0xffffu;
                 const int nv = min(T, R - tA * T);
                 const unsigned all = (full | (full >> 4) | (full >> 8) | (full >> 12)) & ((1u << nv) - 1u);
                 if (G > 1 && lane == 0) atomicExch(&a.tile_bits[tA], 0);
                 if (a.alive && lane < nv) a.alive[rowA] = (int32_t)((all >> lane) & 1u);
-                if (a.yzero) {
-#pragma unroll
-                    for (int t = 0; t < T; ++t) {
-                        if (t < nv && !((all >> t) & 1u)) {
-                            const int r = __builtin_amdgcn_readlane(rowA, t);
-                            float4* z = reinterpret_cast<float4*>(a.yzero + (size_t)r * N);
-                            for (int i = lane; i < N / 4; i += 64) z[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-                        }
-                    }
-                }
                 if (a.list_out && all) {
                     baseB = lane == 0 ? atomicAdd(a.cnt_out, __popc(all)) : 0;
                     maskB = all;
@@ -591,14 +615,15 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
             }
             tA = -1;
         }
-    };
-    auto push_a = [&](int tile, int row, int buf) {
-        mineA = s_bits[buf];
-        if (lane == 0) s_bits[buf] = 0u;
-        oldA = 0u;
-        if (G > 1 && lane == 0) oldA = (unsigned)atomicAdd(&a.tile_bits[tile], (int)((1u << 16) | (mineA << (4 * p))));
-        tA = tile;
-        rowA = row;
+        // the new tile: add this part's row bits to its word
+        if (tile_new >= 0) {
+            mineA = mine_new;
+            oldA = 0u;
+            if (G > 1 && lane == 0)
+                oldA = (unsigned)atomicAdd(&a.tile_bits[tile_new], (int)((1u << 16) | (mine_new << (4 * p))));
+            tA = tile_new;
+            rowA = row_new;
+        }
     };
 
     if (tid == 0) { s_bits[0] = 0u; s_bits[1] = 0u; }
@@ -609,23 +634,30 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
         row_c = a.list_in ? a.list_in[pp] : a.row_base + pp;
         orow_c = (LINEAR && a.rows_out) ? a.rows_out[pp] : row_c;
     }
-    stage(row_c, 0);
+    L.stage(a.yin, row_c, wave, lane, WAVES);
     if (q + S < ntiles) prefetch(q + S, 1);
     float o0[T] = {0.f, 0.f, 0.f, 0.f}, o1[T] = {0.f, 0.f, 0.f, 0.f};
     int tile_p = -1, row_p = 0, orow_p = 0;          // the previous tile (outputs not yet stored)
-    auto store_prev = [&]() {
+    // Outputs of the previous tile.  `mine` = this part's row bits: where a row's slice of
+    // this part is all zero and dead rows must be cleared in another buffer (yzero),
+    // the slice's zeros go there too, so a row that dies is cleared by its parts
+    // without waiting for the other parts.
+    auto store_prev = [&](unsigned mine) {
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             if (tile_p * T + t < R) {
                 const int ro = __builtin_amdgcn_readlane(LINEAR ? orow_p : row_p, t);
                 const size_t base = (size_t)ro * N;
+                const bool zero_slice = !LINEAR && a.yzero && !((mine >> t) & 1u);
                 if (n0.j >= 0) {
                     a.yout[base + n0.j] = o0[t];
                     if (a.ycopy) a.ycopy[base + n0.j] = o0[t];
+                    if (zero_slice) a.yzero[base + n0.j] = 0.f;
                 }
                 if (n1.j >= 0) {
                     a.yout[base + n1.j] = o1[t];
                     if (a.ycopy) a.ycopy[base + n1.j] = o1[t];
+                    if (zero_slice) a.yzero[base + n1.j] = 0.f;
                 }
             }
         }
@@ -634,31 +666,26 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
     for (int tile = q; tile < ntiles; tile += S, ++it) {
         const int buf = it & 1;
         __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
-        __syncthreads();
+        __syncthreads();                             // the tile has landed; the compute tile is free
         if (tile_p >= 0) {
-            store_prev();
-            if (live && wave == 0) {
-                step_b();
-                step_a();
-                push_a(tile_p, row_p, buf ^ 1);
-            }
+            const unsigned mine = (live || a.yzero) ? s_bits[buf ^ 1] : 0xfu;
+            if (live && wave == 0) advance(tile_p, row_p, mine);   // before any store: nothing outstanding
+            store_prev(mine);
         }
+        L.transpose(tid, NT);
+        __syncthreads();                             // compute tile ready; landing area free
+        if (tid == 0) s_bits[buf ^ 1] = 0u;          // every wave has read it
         const int row_now = row_c, orow_now = orow_c;
         if (tile + S < ntiles) {
             // ring slot (it + 1) & 1 holds tile + S's ids (copied a tile ago, waited above)
             row_c = in_row(tile + S, buf ^ 1);
             orow_c = out_row(tile + S, buf ^ 1);
-            stage(row_c, buf ^ 1);
+            L.stage(a.yin, row_c, wave, lane, WAVES);
         }
         if (tile + 2 * S < ntiles) prefetch(tile + 2 * S, buf);
         float acc0[T] = {0.f, 0.f, 0.f, 0.f}, acc1[T] = {0.f, 0.f, 0.f, 0.f};
-        if (buf == 0) {
-            sched_steps<DMAX, 0>(a, lds_base, lane, n0, acc0);
-            sched_steps<DMAX, 0>(a, lds_base, lane, n1, acc1);
-        } else {
-            sched_steps<DMAX, 1>(a, lds_base, lane, n0, acc0);
-            sched_steps<DMAX, 1>(a, lds_base, lane, n1, acc1);
-        }
+        sched_steps<DMAX>(a, L.base, lane, n0, acc0);
+        sched_steps<DMAX>(a, L.base, lane, n1, acc1);
         unsigned bits = 0u;
 #pragma unroll
         for (int t = 0; t < T; ++t) {
@@ -666,8 +693,8 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
             o1[t] = LINEAR ? acc1[t] : fminf(fmaxf(acc1[t] + n1.bj, 0.f), a.clamp);
             bits |= ((o0[t] != 0.f && n0.j >= 0) || (o1[t] != 0.f && n1.j >= 0)) ? (1u << t) : 0u;
         }
-        if (live) {
-            // row liveness: this workgroup's waves meet in LDS (read by wave 0 after the next barrier)
+        if (live || (!LINEAR && a.yzero)) {
+            // row bits of this part: its waves meet in LDS (read after the next barrier)
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o);
             if (lane == 0 && bits) atomicOr(&s_bits[buf], bits);
@@ -679,15 +706,15 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
     // drain: the last tile's outputs and the rest of the liveness pipeline
     __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
     __syncthreads();
-    store_prev();
+    const unsigned mine_last = (live || a.yzero) ? s_bits[(it - 1) & 1] : 0xfu;
     if (live && wave == 0) {
-        step_b();
-        step_a();
-        push_a(tile_p, row_p, (it - 1) & 1);
-        step_b();
-        step_a();
-        step_b();
+        advance(tile_p, row_p, mine_last);
+        __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
+        advance(-1, 0, 0u);
+        __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
+        advance(-1, 0, 0u);
     }
+    store_prev(mine_last);
     __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
 }
 
@@ -755,13 +782,17 @@ __global__ __launch_bounds__(NT) void k_bwd_dy_sched(LayerArgs a) {
 //   acc[st] = sum over its rows of G[r][j] * Y_l[r][id(st)]
 // (rows in ascending order within its tile stream), so a stream's partial sums
 // are deterministic.  The masked gradient G[r][j] = dY[r][j] [0 < Y_{l+1} < c]
-// of its neurons is also written out for the input-gradient pass.
+// of its neurons is also written out for the input-gradient pass.  Tiles of
+// Y_l are staged like the forward kernel's; the Y_{l+1} and dY values a lane
+// needs for a tile are loaded one tile ahead, into the registers the current
+// tile's values have just left.
 template <int NT, int DMAX>
 __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
     extern __shared__ __align__(16) float lds[];
     constexpr int T = SCHED_T;
     constexpr int WAVES = NT / 64;
     const int N = a.N;
+    const SchedLds L(lds, N);
     const int R = *a.nrows;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -773,7 +804,6 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
     const int q = (kk / G) * 8 + x;
     const int S = (int)gridDim.x / G;
     const int ntiles = (R + T - 1) / T;
-    const uint32_t lds_base = (uint32_t)(uintptr_t)lds;
     int j[2], D[2], slot[2];
     uint32_t off[2][DMAX];
     float acc[2][DMAX];
@@ -791,7 +821,7 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
             e[st] = (have && st < D[h]) ? a.ent[(size_t)slot[h] * SCHED_DSTORE + st] : (0x80000000u | 31u);
 #pragma unroll
         for (int st = 0; st < DMAX; ++st) {
-            off[h][st] = lds_base + ((e[st] >> 5) & 0x03ffffffu);
+            off[h][st] = L.base + ((e[st] >> 5) & 0x03ffffffu);
             acc[h][st] = 0.f;
         }
 #pragma unroll
@@ -803,49 +833,62 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
             for (int k = 0; k < K; ++k) pw[k] = 0.f;
         }
     }
-    const int nchunks = N / 16;
-    auto stage = [&](int tile, int buf) {
+    // rows of a tile are consecutive (padding positions repeat the tile's first row)
+    auto row_of = [&](int tile) -> int {
         const int pos = tile * T + (lane & 3);
-        const float* src = a.y_in + (size_t)(pos < R ? pos : tile * T) * N + (lane >> 2);
-        for (int c = wave; c < nchunks; c += WAVES) {
-            const uint32_t dst = __builtin_amdgcn_readfirstlane(lds_base + 512u * c + 256u * buf);
-            const float* gp = src + 16 * c;
-            uint32_t saved;
-            __asm__ volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\tglobal_load_lds_dword %1, off\n\ts_mov_b32 m0, %0"
-                             : "=&s"(saved) : "v"(gp), "s"(dst) : "memory");
-        }
+        return pos < R ? pos : tile * T;
     };
-    int it = 0;
-    if (q < ntiles) stage(q, 0);
-    for (int tile = q; tile < ntiles; tile += S, ++it) {
-        const int buf = it & 1;
-        __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
-        __syncthreads();
-        if (tile + S < ntiles) stage(tile + S, buf ^ 1);
+    float yo[2][T], dv[2][T];      // Y_{l+1} and dY of the lane's neurons for the next tile
+    auto fetch = [&](int tile) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            float g[T];
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int t = 0; t < T; ++t) {
                 const int r = tile * T + t;
-                g[t] = 0.f;
+                yo[h][t] = 0.f;
+                dv[h][t] = 0.f;
                 if (r < R && j[h] >= 0) {
                     const size_t o = (size_t)r * N + j[h];
-                    const float yo = a.y_out[o];
-                    g[t] = (yo > 0.f && yo < a.clamp) ? a.dy[o] : 0.f;
-                    a.g_out[o] = g[t];
+                    yo[h][t] = a.y_out[o];
+                    dv[h][t] = a.dy[o];
                 }
-                accb[h] += g[t];
             }
+    };
+    if (q < ntiles) {
+        L.stage(a.y_in, row_of(q), wave, lane, WAVES);
+        fetch(q);
+    }
+    for (int tile = q; tile < ntiles; tile += S) {
+        __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
+        __syncthreads();
+        L.transpose(tid, NT);
+        __syncthreads();
+        // G of this tile from the values fetched a tile ago (before any copy is issued,
+        // so reading them waits for nothing new)
+        float g[2][T];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                g[h][t] = (yo[h][t] > 0.f && yo[h][t] < a.clamp) ? dv[h][t] : 0.f;
+                accb[h] += g[h][t];
+                if (tile * T + t < R && j[h] >= 0) a.g_out[(size_t)(tile * T + t) * N + j[h]] = g[h][t];
+            }
+        if (tile + S < ntiles) {
+            L.stage(a.y_in, row_of(tile + S), wave, lane, WAVES);
+            fetch(tile + S);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
 #pragma unroll
             for (int st = 0; st < DMAX; ++st) {
                 if (st < D[h]) {
-                    const float4 v = buf == 0 ? lds_read16(off[h][st]) : lds_read16(off[h][st] + 256);
+                    const float4 v = lds_read16(off[h][st]);
                     float s = acc[h][st];
-                    s = fmaf(g[0], v.x, s);
-                    s = fmaf(g[1], v.y, s);
-                    s = fmaf(g[2], v.z, s);
-                    s = fmaf(g[3], v.w, s);
+                    s = fmaf(g[h][0], v.x, s);
+                    s = fmaf(g[h][1], v.y, s);
+                    s = fmaf(g[h][2], v.z, s);
+                    s = fmaf(g[h][3], v.w, s);
                     acc[h][st] = s;
                 }
             }
@@ -854,12 +897,12 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
                 for (int st = DMAX; st < D[h]; ++st) {
                     const uint32_t e = a.ent[(size_t)slot[h] * SCHED_DSTORE + st];
                     if (e & 0x80000000u) continue;
-                    const float4 v = lds_read16(lds_base + ((e >> 5) & 0x03ffffffu) + 256u * buf);
+                    const float4 v = lds_read16(L.base + ((e >> 5) & 0x03ffffffu));
                     float s = pw[e & 31u];
-                    s = fmaf(g[0], v.x, s);
-                    s = fmaf(g[1], v.y, s);
-                    s = fmaf(g[2], v.z, s);
-                    s = fmaf(g[3], v.w, s);
+                    s = fmaf(g[h][0], v.x, s);
+                    s = fmaf(g[h][1], v.y, s);
+                    s = fmaf(g[h][2], v.z, s);
+                    s = fmaf(g[h][3], v.w, s);
                     pw[e & 31u] = s;
                 }
             }
