@@ -336,32 +336,46 @@ struct SchedLds {
     float* C;             // [N][4]
     float* A;             // [4][N]
     unsigned* scalars;    // 32 words
+    float* out;           // [4][SCHED_PART] outputs of the workgroup's part for one tile
     uint32_t base;        // LDS byte address of C
     uint32_t land;        // LDS byte address of A
     uint32_t ovf;         // LDS byte address of the overflow area
     int N;
     __device__ __forceinline__ SchedLds(float* lds, int n)
         : C(lds), A(lds + 4 * n), scalars(reinterpret_cast<unsigned*>(lds + 8 * n)),
-          base((uint32_t)(uintptr_t)lds), land((uint32_t)(uintptr_t)lds + 16u * n),
-          ovf((uint32_t)(uintptr_t)lds + 32u * n + SCHED_SCALARS), N(n) {}
-    // Issue the copies of 4 rows of src into A; row t's id is in lane t of `row`.
-    // 1 KB pieces (256 floats of one row), wave w issuing pieces w, w + waves, ...
-    __device__ __forceinline__ void stage(const float* src, int row, int wave, int lane, int waves) const {
+          out(lds + 8 * n + SCHED_SCALARS / 4), base((uint32_t)(uintptr_t)lds),
+          land((uint32_t)(uintptr_t)lds + 16u * n),
+          ovf((uint32_t)(uintptr_t)lds + 32u * n + SCHED_SCALARS + SCHED_OUT), N(n) {}
+    // The copies of 4 rows of src into A come in 1 KB pieces (256 floats of one row);
+    // wave w issues pieces w, w + waves, ...  Row t's id is in lane t of `row`.
+    __device__ __forceinline__ int pieces(int wave, int waves) const {
+        const int total = SCHED_T * ((N + 255) >> 8);
+        return wave < total ? (total - wave + waves - 1) / waves : 0;
+    }
+    __device__ __forceinline__ void stage_piece(const float* src, int row, int wave, int lane, int waves, int i) const {
         const int P = (N + 255) >> 8;
-        for (int c = wave; c < SCHED_T * P; c += waves) {
-            const int r = c / P;
-            const int col = 256 * (c - r * P);
-            const int rid = __builtin_amdgcn_readlane(row, r);
-            const int n = col + 4 * lane;
-            if (n < N) {
-                const float* g = src + (size_t)rid * N + n;
-                const uint32_t dst = __builtin_amdgcn_readfirstlane(land + 4u * (uint32_t)(r * N + col));
-                uint32_t saved;
-                __asm__ volatile(
-                    "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %1, off\n\ts_mov_b32 m0, %0"
-                    : "=&s"(saved) : "v"(g), "s"(dst) : "memory");
-            }
+        const int c = wave + i * waves;
+        const int r = c / P;
+        const int col = 256 * (c - r * P);
+        const int rid = __builtin_amdgcn_readlane(row, r);
+        if (col + 4 * lane < N) {
+            // scalar base (the piece's first float) + 16 bytes per lane: no per-lane 64-bit address
+            const uint64_t gb = (uint64_t)(uintptr_t)(src + (size_t)rid * N + col);
+            // (readfirstlane returns int: widen through uint32_t, never by sign extension)
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)gb);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(gb >> 32));
+            const uint64_t sb = ((uint64_t)hi << 32) | (uint64_t)lo;
+            const uint32_t voff = 16u * (uint32_t)lane;
+            const uint32_t dst = __builtin_amdgcn_readfirstlane(land + 4u * (uint32_t)(r * N + col));
+            uint32_t saved;
+            __asm__ volatile(
+                "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %3\n\tglobal_load_lds_dwordx4 %1, %2\n\ts_mov_b32 m0, %0"
+                : "=&s"(saved) : "v"(voff), "s"(sb), "s"(dst) : "memory");
         }
+    }
+    __device__ __forceinline__ void stage(const float* src, int row, int wave, int lane, int waves) const {
+        const int np = pieces(wave, waves);
+        for (int i = 0; i < np; ++i) stage_piece(src, row, wave, lane, waves, i);
     }
     // A (row-major) -> C ([id][row]); the caller brackets it with barriers.  Eight ids
     // per thread per round, all reads issued before the writes.
@@ -471,9 +485,12 @@ struct SchedNeuron {
     }
 };
 
-template <int DMAX>
+// hook(g) runs at the start of group g (for every g with 4g < D): the caller's way
+// of spreading memory instructions over the compute instead of issuing them in a
+// burst that fills the memory pipeline and blocks the waves at issue.
+template <int DMAX, typename Hook>
 __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_base, int lane, const SchedNeuron<DMAX>& n,
-                                            float (&acc)[SCHED_T]) {
+                                            float (&acc)[SCHED_T], Hook&& hook) {
     // Steps in groups of 4; the reads of group g+1 are issued before the FMAs of
     // group g (ping-pong register sets).  Steps past D are padding (weight 0, a
     // conflict-free read), so reading one group ahead is always safe.
@@ -485,6 +502,7 @@ __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_bas
 #pragma unroll
     for (int g = 0; g < DMAX / 4; ++g) {
         if (4 * g < D) {
+            hook(g);
             if (g + 1 < DMAX / 4) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) v[(g + 1) & 1][u] = lds_read16(n.off[4 * (g + 1) + u]);
@@ -636,29 +654,29 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
     }
     L.stage(a.yin, row_c, wave, lane, WAVES);
     if (q + S < ntiles) prefetch(q + S, 1);
-    float o0[T] = {0.f, 0.f, 0.f, 0.f}, o1[T] = {0.f, 0.f, 0.f, 0.f};
     int tile_p = -1, row_p = 0, orow_p = 0;          // the previous tile (outputs not yet stored)
-    // Outputs of the previous tile.  `mine` = this part's row bits: where a row's slice of
-    // this part is all zero and dead rows must be cleared in another buffer (yzero),
-    // the slice's zeros go there too, so a row that dies is cleared by its parts
-    // without waiting for the other parts.
-    auto store_prev = [&](unsigned mine) {
+    const int part0 = p * SCHED_PART;                // first neuron of this part
+    const int width = min(SCHED_PART, N - part0);    // its neurons
+    // Outputs of the previous tile, from the staging tile: 16 bytes per lane per store,
+    // each wave's 256 floats within one row.  `mine` = this part's row bits: where a
+    // row's slice of this part is all zero and dead rows must be cleared in another
+    // buffer (yzero), the slice's zeros go there too, so a row that dies is cleared by
+    // its parts without waiting for the other parts.
+    auto store_tile = [&](unsigned mine) {
+        const int nv = min(T, R - tile_p * T);
 #pragma unroll
-        for (int t = 0; t < T; ++t) {
-            if (tile_p * T + t < R) {
+        for (int k = 0; k < T * SCHED_PART / 4 / NT; ++k) {
+            const int e = (k * NT + tid) * 4;
+            const int t = __builtin_amdgcn_readfirstlane(e / SCHED_PART);
+            const int col = e % SCHED_PART;
+            if (t < nv && col < width) {
                 const int ro = __builtin_amdgcn_readlane(LINEAR ? orow_p : row_p, t);
-                const size_t base = (size_t)ro * N;
-                const bool zero_slice = !LINEAR && a.yzero && !((mine >> t) & 1u);
-                if (n0.j >= 0) {
-                    a.yout[base + n0.j] = o0[t];
-                    if (a.ycopy) a.ycopy[base + n0.j] = o0[t];
-                    if (zero_slice) a.yzero[base + n0.j] = 0.f;
-                }
-                if (n1.j >= 0) {
-                    a.yout[base + n1.j] = o1[t];
-                    if (a.ycopy) a.ycopy[base + n1.j] = o1[t];
-                    if (zero_slice) a.yzero[base + n1.j] = 0.f;
-                }
+                const size_t o = (size_t)ro * N + part0 + col;
+                const float4 v = *reinterpret_cast<const float4*>(L.out + e);
+                *reinterpret_cast<float4*>(a.yout + o) = v;
+                if (a.ycopy) *reinterpret_cast<float4*>(a.ycopy + o) = v;
+                if (!LINEAR && a.yzero && !((mine >> t) & 1u))
+                    *reinterpret_cast<float4*>(a.yzero + o) = make_float4(0.f, 0.f, 0.f, 0.f);
             }
         }
     };
@@ -670,28 +688,35 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
         if (tile_p >= 0) {
             const unsigned mine = (live || a.yzero) ? s_bits[buf ^ 1] : 0xfu;
             if (live && wave == 0) advance(tile_p, row_p, mine);   // before any store: nothing outstanding
-            store_prev(mine);
+            store_tile(mine);
         }
         L.transpose(tid, NT);
         __syncthreads();                             // compute tile ready; landing area free
         if (tid == 0) s_bits[buf ^ 1] = 0u;          // every wave has read it
         const int row_now = row_c, orow_now = orow_c;
-        if (tile + S < ntiles) {
+        const bool more = tile + S < ntiles;
+        if (more) {
             // ring slot (it + 1) & 1 holds tile + S's ids (copied a tile ago, waited above)
             row_c = in_row(tile + S, buf ^ 1);
             orow_c = out_row(tile + S, buf ^ 1);
-            L.stage(a.yin, row_c, wave, lane, WAVES);
         }
         if (tile + 2 * S < ntiles) prefetch(tile + 2 * S, buf);
+        // the next tile's copies, spread over the first neuron's groups
+        const int np = more ? L.pieces(wave, WAVES) : 0;
         float acc0[T] = {0.f, 0.f, 0.f, 0.f}, acc1[T] = {0.f, 0.f, 0.f, 0.f};
-        sched_steps<DMAX>(a, L.base, lane, n0, acc0);
-        sched_steps<DMAX>(a, L.base, lane, n1, acc1);
+        sched_steps<DMAX>(a, L.base, lane, n0, acc0, [&](int g) {
+            if (g < np) L.stage_piece(a.yin, row_c, wave, lane, WAVES, g);
+        });
+        for (int i = min(np, (n0.D + 3) >> 2); i < np; ++i) L.stage_piece(a.yin, row_c, wave, lane, WAVES, i);
+        sched_steps<DMAX>(a, L.base, lane, n1, acc1, [](int) {});
         unsigned bits = 0u;
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-            o0[t] = LINEAR ? acc0[t] : fminf(fmaxf(acc0[t] + n0.bj, 0.f), a.clamp);
-            o1[t] = LINEAR ? acc1[t] : fminf(fmaxf(acc1[t] + n1.bj, 0.f), a.clamp);
-            bits |= ((o0[t] != 0.f && n0.j >= 0) || (o1[t] != 0.f && n1.j >= 0)) ? (1u << t) : 0u;
+            const float o0 = LINEAR ? acc0[t] : fminf(fmaxf(acc0[t] + n0.bj, 0.f), a.clamp);
+            const float o1 = LINEAR ? acc1[t] : fminf(fmaxf(acc1[t] + n1.bj, 0.f), a.clamp);
+            if (n0.j >= 0) L.out[t * SCHED_PART + (n0.j - part0)] = o0;
+            if (n1.j >= 0) L.out[t * SCHED_PART + (n1.j - part0)] = o1;
+            bits |= ((o0 != 0.f && n0.j >= 0) || (o1 != 0.f && n1.j >= 0)) ? (1u << t) : 0u;
         }
         if (live || (!LINEAR && a.yzero)) {
             // row bits of this part: its waves meet in LDS (read after the next barrier)
@@ -714,7 +739,7 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
         __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
         advance(-1, 0, 0u);
     }
-    store_prev(mine_last);
+    store_tile(mine_last);
     __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
 }
 

@@ -68,14 +68,15 @@ constexpr int SCHED_T = 4;       // rows per tile of the scheduled kernel
 constexpr int SCHED_NT = 512;    // its workgroup size (each lane owns two neurons)
 constexpr int SCHED_DMAX = 40;   // schedule steps held in registers
 constexpr int SCHED_DSTORE = 64; // schedule steps stored per lane
-constexpr int SCHED_OVF = 40;    // block-steps past SCHED_DMAX a workgroup keeps in LDS (512 bytes each)
-
+constexpr int SCHED_OVF = 8;     // block-steps past SCHED_DMAX a workgroup keeps in LDS (512 bytes each)
 constexpr int SCHED_SCALARS = 128; // bytes of per-workgroup scalars after the tile buffers
+constexpr int SCHED_PART = 1024;   // neurons per workgroup ("part") of the scheduled kernels
+constexpr int SCHED_OUT = SCHED_T * SCHED_PART * 4;   // bytes of the output staging tile
 
-// LDS of the scheduled forward kernel: two 4-row tile buffers, the scalars, the
-// overflow area.
+// LDS of the scheduled forward kernel: compute tile and landing area (4 rows of N
+// floats each), the scalars, the output staging tile, the overflow area.
 inline size_t sched_lds_bytes(int N) {
-    return (size_t)2 * SCHED_T * N * sizeof(float) + SCHED_SCALARS + (size_t)SCHED_OVF * 512;
+    return (size_t)2 * SCHED_T * N * sizeof(float) + SCHED_SCALARS + SCHED_OUT + (size_t)SCHED_OVF * 512;
 }
 
 // Whole forward pass run by the persistent kernel (all layers, one launch).
