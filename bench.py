@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--cpu", dest="cpu", action="store_true", default=True)
     ap.add_argument("--no-cpu", dest="cpu", action="store_false")
     ap.add_argument("--cpu-rows", type=int, default=3000, help="row sample for the oracle baseline")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes 5 times (the reference kernel for the "
+                         "FETCH_SIZE / WRITE_SIZE counter scale) and exit")
     ap.add_argument("--tune", action="store_true", default=True)
     ap.add_argument("--no-tune", dest="tune", action="store_false")
     return ap.parse_args()
@@ -68,11 +71,13 @@ def live_edges(prof, N, L):
     return sum(int(prof[l]) for l in range(L)) * N * K
 
 
-def time_forward(torch, net, y0, out, steps, warmup, batch_off=None):
+def time_forward(torch, net, y0, out, steps, warmup, batch_off=None, on_start=None):
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         net.forward(y0, batch_off=batch_off, out=out)
     torch.cuda.synchronize()
+    if on_start is not None:
+        on_start()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(steps):
@@ -100,6 +105,15 @@ def main():
         b.build()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        n = args.calibrate_copy // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 4, "launches": 5}))
+        return
 
     cfg = gen.CONFIGS["C2"]
     N, L, B = cfg.n_neurons, cfg.n_layers, cfg.rows
@@ -128,16 +142,31 @@ def main():
     log("warm-up engine times (ms)", engines, "->", engine)
 
     # ---------------------------------------------------------------- timed region
-    ms = time_forward(torch, net, y0, out, args.steps, args.warmup)
+    # In persistent mode the library brackets its chain kernel with HIP events on the
+    # stream it launches on; those give the dominant kernel's own average duration.
+    timed_kernel = engine == "persistent"
+    if timed_kernel:
+        net.set_timing(True)
+    ms = time_forward(torch, net, y0, out, args.steps, args.warmup,
+                      on_start=(lambda: net.kernel_time()) if timed_kernel else None)   # drop warm-up events
+    k_ms, k_n = net.kernel_time() if timed_kernel else (0.0, 0)
+    if timed_kernel:
+        net.set_timing(False)
+        k_avg = k_ms / k_n if k_n else ms
     prof = out["layer_rows"].cpu().numpy()
     n_nz = int(out["n_nz"].item())
     value = B * nnz / (ms / 1e3)
     alg = forward_bytes(prof, N, L)
-    achieved = alg / (ms / 1e3) / 1e9
-    kernel = "k_chain (persistent forward, all layers)" if engine == "persistent" else "k_layer (480 graph nodes)"
+    if timed_kernel:
+        kernel = "sdnn::k_chain_sched<512, 40> (persistent forward, all layers, one launch per step)"
+        alg_launch, dur_ms = alg, k_avg
+    else:
+        kernel = "sdnn::k_layer_sched<512, 40> (one graph node per layer; step time / layers)"
+        alg_launch, dur_ms = alg / L, ms / L
+    achieved = alg_launch / (dur_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
-                "alg_bytes_per_launch": alg if engine == "persistent" else alg / L}
+                "alg_bytes_per_launch": alg_launch, "avg_launch_ms": round(dur_ms, 4)}
     log(f"C2 {engine}: {ms:.3f} ms/step, {value:.3e} edges/s, profile head {prof[:5].tolist()}, nz {n_nz}")
 
     extras = {"engines_ms": {k: round(v, 4) for k, v in engines.items()}, "plan": net.plan,

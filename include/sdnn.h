@@ -115,6 +115,18 @@ sdnn_status sdnn_set_exec(sdnn_net net, int32_t mode);
 /* Read the current tile plan. */
 sdnn_status sdnn_get_plan(sdnn_net net, sdnn_plan *plan);
 
+/*
+ * Kernel timing (measurement support, not part of the method).  With enable != 0,
+ * every sdnn_forward in SDNN_EXEC_PERSISTENT mode records a pair of HIP events
+ * around its persistent layer-chain kernel, on the stream it is launched on.
+ * sdnn_kernel_time waits for the recorded events and returns the summed kernel
+ * time in milliseconds and the number of launches since the previous call (or
+ * since timing was enabled), then starts a new sum.  Either output pointer may
+ * be NULL.  Events are created on first use and released by sdnn_destroy.
+ */
+sdnn_status sdnn_set_timing(sdnn_net net, int32_t enable);
+sdnn_status sdnn_kernel_time(sdnn_net net, double *total_ms, int32_t *launches);
+
 /* Time every kernel variant that fits on a full-live layer of `rows` rows (rows <=
  * max_rows; uses the workspace as scratch) and keep the fastest.  Synchronizes. */
 sdnn_status sdnn_tune(sdnn_net net, int64_t rows, void *stream);

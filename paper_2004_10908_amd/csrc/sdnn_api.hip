@@ -58,7 +58,7 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Layout {
     size_t act = 0, list0 = 0, list1 = 0, alive = 0, cnt = 0, bar = 0, err = 0, flag = 0;
-    size_t ent = 0, lane_neuron = 0, wave_steps = 0, tile_bits = 0;
+    size_t ent = 0, lane_neuron = 0, wave_steps = 0, tile_bits = 0, prog = 0;
     size_t ent_t = 0, ent_w = 0, lane_input = 0, steps_t = 0, gbuf2 = 0;
     bool sched = false;
     size_t tr_ptr = 0, tr_e = 0, seg = 0, gbuf0 = 0, gbuf1 = 0, pdw = 0, pdb = 0;
@@ -98,6 +98,7 @@ Layout make_layout(const sdnn_desc& d) {
         y.lane_neuron = take(L * npad * 4);
         y.wave_steps = take(L * nblk * 4);
         y.tile_bits = take(((R + SCHED_T - 1) / SCHED_T) * 4);
+        y.prog = take(SCHED_PROG * 4);
     }
     y.bar = take(NBAR * 4);
     y.err = take(64);
@@ -155,6 +156,7 @@ struct Launch {
     dim3 grid, block;
     size_t shmem = 0;
     bool cooperative = false;
+    bool timed = false;                 // bracketed by timing events when the net's timing is on
     std::vector<void*> ptrs;
 };
 
@@ -196,7 +198,7 @@ struct sdnn_net_s {
     bool compaction = true;
     bool sched = false;                 // scheduled kernel available (schedule built)
     uint32_t* ent = nullptr;
-    int32_t *lane_neuron = nullptr, *wave_steps = nullptr, *tile_bits = nullptr;
+    int32_t *lane_neuron = nullptr, *wave_steps = nullptr, *tile_bits = nullptr, *prog = nullptr;
     int parts = 1, nblk = 0;
     bool sched_bwd = false;             // transposed schedule built (scheduled backward)
     uint32_t *ent_t = nullptr, *ent_w = nullptr;
@@ -212,6 +214,9 @@ struct sdnn_net_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::vector<int64_t> gkey;
+    bool timing = false;                 // sdnn_set_timing
+    std::vector<hipEvent_t> tev;         // start/stop pairs, created on first use
+    size_t tev_used = 0;                 // events recorded since the last sdnn_kernel_time
 };
 
 namespace {
@@ -232,6 +237,7 @@ void fill_sched(const sdnn_net_s* n, LayerArgs& a, int l) {
     a.lane_neuron = n->lane_neuron + (size_t)l * npad;
     a.wave_steps = n->wave_steps + (size_t)l * n->nblk;
     a.tile_bits = n->tile_bits;
+    a.prog = n->prog;
     a.parts = n->parts;
     a.nblk = n->nblk;
 }
@@ -287,13 +293,28 @@ int default_variant(const sdnn_net_s* n) {
     return 0;
 }
 
-sdnn_status issue(const Plan& plan, hipStream_t s) {
+sdnn_status issue(const Plan& plan, hipStream_t s, sdnn_net_s* n = nullptr) {
     for (const auto& L : plan) {
+        const bool timed = n && n->timing && L->timed;
+        if (timed) {
+            if (n->tev_used + 2 > n->tev.size()) {
+                for (int i = 0; i < 2; ++i) {
+                    hipEvent_t e;
+                    HIPCHK(hipEventCreate(&e));
+                    n->tev.push_back(e);
+                }
+            }
+            HIPCHK(hipEventRecord(n->tev[n->tev_used], s));
+        }
         if (L->cooperative) {
             HIPCHK(hipLaunchCooperativeKernel(L->fn, L->grid, L->block, const_cast<void**>(L->ptrs.data()),
                                               (unsigned)L->shmem, s));
         } else {
             HIPCHK(hipLaunchKernel(L->fn, L->grid, L->block, const_cast<void**>(L->ptrs.data()), L->shmem, s));
+        }
+        if (timed) {
+            HIPCHK(hipEventRecord(n->tev[n->tev_used + 1], s));
+            n->tev_used += 2;
         }
     }
     return SDNN_OK;
@@ -421,11 +442,13 @@ Plan plan_persistent(const sdnn_net_s* n, const float* y0, int64_t rows, float* 
         c.lane_neuron = n->lane_neuron;
         c.wave_steps = n->wave_steps;
         c.tile_bits = n->tile_bits;
+        c.prog = n->prog;
         c.parts = n->parts;
         c.nblk = n->nblk;
     }
     auto ch = mk(v.chain_fn, dim3(n->chain_grid), dim3(v.NT), sh, c);
     ch->cooperative = true;
+    ch->timed = true;
     p.push_back(std::move(ch));
     p.push_back(mk((const void*)&k_finalize, dim3(1), dim3(1024), 0, (const int32_t*)n->alive, (int32_t)rows, nz_rows,
                    n_nz, (const int32_t*)n->cnt, (int32_t)1, (int32_t)L, layer_rows));
@@ -617,6 +640,7 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
         n->lane_neuron = (int32_t*)(n->ws + lay.lane_neuron);
         n->wave_steps = (int32_t*)(n->ws + lay.wave_steps);
         n->tile_bits = (int32_t*)(n->ws + lay.tile_bits);
+        n->prog = (int32_t*)(n->ws + lay.prog);
         std::vector<int32_t> hidx((size_t)L * N * K);
         HIPCHK(hipMemcpyAsync(hidx.data(), idx, hidx.size() * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -637,6 +661,7 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
                 HIPCHK(hipMemcpyAsync(n->wave_steps, hws.data(), hws.size() * 4, hipMemcpyHostToDevice, s));
                 const int64_t nt = (std::max<int64_t>(desc->max_rows, 1) + SCHED_T - 1) / SCHED_T;
                 hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nt)), dim3(256), 0, s, n->tile_bits, nt, 0);
+                hipLaunchKernelGGL(k_fill_i32, dim3(4), dim3(256), 0, s, n->prog, (int64_t)SCHED_PROG, 0);
                 HIPCHK(hipGetLastError());
                 HIPCHK(hipStreamSynchronize(s));
                 n->sched = true;
@@ -694,6 +719,27 @@ sdnn_status sdnn_set_exec(sdnn_net net, int32_t mode) {
     if (!net) return fail(SDNN_EINVAL, "net is NULL");
     if (mode < SDNN_EXEC_AUTO || mode > SDNN_EXEC_GRAPH_MERGED) return fail(SDNN_EINVAL, "unknown exec mode %d", mode);
     net->exec = mode;
+    return SDNN_OK;
+}
+
+sdnn_status sdnn_set_timing(sdnn_net net, int32_t enable) {
+    if (!net) return fail(SDNN_EINVAL, "net is NULL");
+    net->timing = enable != 0;
+    return SDNN_OK;
+}
+
+sdnn_status sdnn_kernel_time(sdnn_net net, double* total_ms, int32_t* launches) {
+    if (!net) return fail(SDNN_EINVAL, "net is NULL");
+    double tot = 0.0;
+    for (size_t i = 0; i + 1 < net->tev_used; i += 2) {
+        HIPCHK(hipEventSynchronize(net->tev[i + 1]));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, net->tev[i], net->tev[i + 1]));
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = (int32_t)(net->tev_used / 2);
+    net->tev_used = 0;
     return SDNN_OK;
 }
 
@@ -807,7 +853,7 @@ sdnn_status sdnn_forward(sdnn_net net, const float* y0, int64_t rows, const int6
     if (mode == SDNN_EXEC_AUTO) mode = n_batches > 1 ? SDNN_EXEC_GRAPH_MERGED : SDNN_EXEC_GRAPH;
     if (mode == SDNN_EXEC_PERSISTENT) {
         Plan p = plan_persistent(net, y0, rows, y_out, nz_rows, n_nz, ckpt, layer_rows);
-        return issue(p, s);
+        return issue(p, s, net);
     }
     // GRAPH / EAGER: batches one after another; GRAPH_MERGED: one chain over all rows.
     const bool merged = mode == SDNN_EXEC_GRAPH_MERGED;
@@ -1056,6 +1102,8 @@ sdnn_status sdnn_check_device(sdnn_net net, void* stream) {
 void sdnn_destroy(sdnn_net net) {
     if (!net) return;
     drop_graph(net);
+    for (hipEvent_t e : net->tev) (void)hipEventDestroy(e);
+    net->tev.clear();
     delete net;
 }
 

@@ -405,6 +405,28 @@ __device__ __forceinline__ void lds_copy4(const int32_t* src, int* dst_lds) {
                      : "=&s"(saved) : "v"(src), "s"(dst) : "memory");
 }
 
+// The same for words other workgroups keep changing: a device-scope read (sc1)
+// that skips this CU's vector cache.
+__device__ __forceinline__ void lds_copy4_coherent(const int32_t* src, int* dst_lds) {
+    const uint32_t dst = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)dst_lds);
+    uint32_t saved;
+    __asm__ volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\tglobal_load_lds_dword %1, off sc1\n\ts_mov_b32 m0, %0"
+                     : "=&s"(saved) : "v"(src), "s"(dst) : "memory");
+}
+
+// Loose lockstep of the parts of a tile stream.  The G workgroups that share a
+// tile read the same 64 KB from memory; when they run within a few tiles of each
+// other, the L2 serves most of those reads, but parts with lighter schedules drift
+// ahead (by tens of tiles over a layer).  Each part publishes its tile count;
+// a part more than SCHED_AHEAD tiles ahead of its slowest sibling waits for it,
+// for at most SCHED_WAIT_TICKS of the 100 MHz clock, and then goes on regardless:
+// this is a cache-locality measure only, results never depend on it.
+constexpr int SCHED_AHEAD = 2;
+constexpr uint64_t SCHED_WAIT_TICKS = 2000;   // 20 us per tile
+__device__ __forceinline__ int part_progress(int v, unsigned tag) {
+    return ((unsigned)v & 0xfff00000u) == tag ? (int)((unsigned)v & 0xfffffu) : -1;
+}
+
 // 16-byte LDS read at an absolute LDS byte address (the offsets already include
 // the workgroup's LDS base), so the address register is used as is.
 __device__ __forceinline__ float4 lds_read16(uint32_t addr) {
@@ -565,6 +587,7 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
     unsigned* s_bits = L.scalars;                         // [2] row bits of the last two tiles
     int* s_pin = reinterpret_cast<int*>(L.scalars) + 8;   // [2][4] input rows of coming tiles
     int* s_pout = reinterpret_cast<int*>(L.scalars) + 16; // [2][4] output rows (linear mode)
+    int* s_prog = reinterpret_cast<int*>(L.scalars) + 24; // [4] the parts' progress words, a tile old
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -581,6 +604,8 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
     n0.load(a, p * 16, p * 16 + 2 * wave, lane, L.base, L.ovf, lds);
     n1.load(a, p * 16, p * 16 + 2 * wave + 1, lane, L.base, L.ovf, lds);
     const bool live = !LINEAR && (a.list_out || a.alive);
+    int* prog_q = (G > 1 && a.prog) ? a.prog + 4 * q : nullptr;   // this stream's progress words
+    const unsigned tag = ((unsigned)a.layer & 0xfffu) << 20;
     // Row ids: lane l carries the id of tile row l % 4.  With a work list (and in linear
     // mode with an output row map) the ids of the tile after next are copied by wave 0
     // into an LDS ring with asynchronous copies, so no register waits on a memory load
@@ -684,6 +709,24 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
     for (int tile = q; tile < ntiles; tile += S, ++it) {
         const int buf = it & 1;
         __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
+        if (prog_q && tid == 0) {
+            __hip_atomic_store(prog_q + p, (int)(tag | (unsigned)it), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (it > SCHED_AHEAD) {
+                int mn = it;
+                for (int pp = 0; pp < G; ++pp) mn = min(mn, part_progress(s_prog[pp], tag));
+                if (mn < it - SCHED_AHEAD) {
+                    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+                    while (__builtin_amdgcn_s_memrealtime() - t0 < SCHED_WAIT_TICKS) {
+                        __builtin_amdgcn_s_sleep(1);
+                        mn = it;
+                        for (int pp = 0; pp < G; ++pp)
+                            mn = min(mn, part_progress(__hip_atomic_load(prog_q + pp, __ATOMIC_RELAXED,
+                                                                         __HIP_MEMORY_SCOPE_AGENT), tag));
+                        if (mn >= it - SCHED_AHEAD) break;
+                    }
+                }
+            }
+        }
         __syncthreads();                             // the tile has landed; the compute tile is free
         if (tile_p >= 0) {
             const unsigned mine = (live || a.yzero) ? s_bits[buf ^ 1] : 0xfu;
@@ -701,6 +744,7 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
             orow_c = out_row(tile + S, buf ^ 1);
         }
         if (tile + 2 * S < ntiles) prefetch(tile + 2 * S, buf);
+        if (prog_q && wave == 0 && lane < G) lds_copy4_coherent(prog_q + lane, s_prog + lane);
         // the next tile's copies, spread over the first neuron's groups
         const int np = more ? L.pieces(wave, WAVES) : 0;
         float acc0[T] = {0.f, 0.f, 0.f, 0.f}, acc1[T] = {0.f, 0.f, 0.f, 0.f};
@@ -785,6 +829,7 @@ __global__ __launch_bounds__(NT) void k_chain_sched(ChainArgs c) {
         a.lane_neuron = c.lane_neuron + (size_t)l * npad;
         a.wave_steps = c.wave_steps + (size_t)l * c.nblk;
         a.tile_bits = c.tile_bits;
+        a.prog = c.prog;
         a.parts = c.parts;
         a.nblk = c.nblk;
         run_layer_sched<NT, DMAX>(a, lds, R);

@@ -38,6 +38,7 @@ struct LayerArgs {
     const int32_t* lane_neuron;  // [npad] neuron of each lane slot (-1: none)
     const int32_t* wave_steps;   // [nblk] steps of each 64-neuron block
     int32_t* tile_bits;          // [max tiles] (parts done << 16) | per-part row bits, zero between layers
+    int32_t* prog;               // [streams][4] tile counts of the parts of each tile stream (lockstep hint)
     int32_t parts;               // G: workgroups sharing a tile (each owns NT neurons)
     int32_t nblk;                // 64-neuron blocks
     // linear (input-gradient) use of the scheduled kernel: weights come from
@@ -70,6 +71,7 @@ constexpr int SCHED_DMAX = 40;   // schedule steps held in registers
 constexpr int SCHED_DSTORE = 64; // schedule steps stored per lane
 constexpr int SCHED_OVF = 8;     // block-steps past SCHED_DMAX a workgroup keeps in LDS (512 bytes each)
 constexpr int SCHED_SCALARS = 128; // bytes of per-workgroup scalars after the tile buffers
+constexpr int SCHED_PROG = 1024;   // ints of the parts' progress words ([streams][4])
 constexpr int SCHED_PART = 1024;   // neurons per workgroup ("part") of the scheduled kernels
 constexpr int SCHED_OUT = SCHED_T * SCHED_PART * 4;   // bytes of the output staging tile
 
@@ -105,6 +107,7 @@ struct ChainArgs {
     const int32_t* lane_neuron;  // [L][npad]
     const int32_t* wave_steps;   // [L][nblk]
     int32_t* tile_bits;
+    int32_t* prog;
     int32_t parts;
     int32_t nblk;
 };

@@ -47,6 +47,8 @@ PROTOTYPES = [
     ("sdnn_create", _I32, [ctypes.POINTER(sdnn_desc), _P, _P, _P, _P, _SZ, _P, ctypes.POINTER(_P)]),
     ("sdnn_set_exec", _I32, [_P, _I32]),
     ("sdnn_get_plan", _I32, [_P, ctypes.POINTER(sdnn_plan)]),
+    ("sdnn_set_timing", _I32, [_P, _I32]),
+    ("sdnn_kernel_time", _I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I32)]),
     ("sdnn_tune", _I32, [_P, _I64, _P]),
     ("sdnn_forward", _I32, [_P, _P, _I64, _P, _I32, _P, _P, _P, _P, _P, _P]),
     ("sdnn_layer", _I32, [_P, _I32, _P, _I64, _P, _P]),
@@ -137,6 +139,17 @@ def sdnn_get_plan(h) -> dict:
             "tuned_us": p.tuned_us}
 
 
+def sdnn_set_timing(h, enable: bool) -> None:
+    _chk(lib().sdnn_set_timing(h, 1 if enable else 0), "sdnn_set_timing")
+
+
+def sdnn_kernel_time(h):
+    """(summed milliseconds, launches) of the timed persistent chain kernels since the last call."""
+    ms, n = ctypes.c_double(0.0), _I32(0)
+    _chk(lib().sdnn_kernel_time(h, ctypes.byref(ms), ctypes.byref(n)), "sdnn_kernel_time")
+    return ms.value, n.value
+
+
 def sdnn_tune(h, rows: int, stream=None) -> None:
     _chk(lib().sdnn_tune(h, rows, _stream(stream)), "sdnn_tune")
 
@@ -225,6 +238,12 @@ class Net:
     @property
     def plan(self) -> dict:
         return sdnn_get_plan(self.h)
+
+    def set_timing(self, enable: bool) -> None:
+        sdnn_set_timing(self.h, enable)
+
+    def kernel_time(self):
+        return sdnn_kernel_time(self.h)
 
     def tune(self, rows: int, stream=None) -> dict:
         sdnn_tune(self.h, rows, stream)
