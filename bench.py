@@ -67,6 +67,31 @@ def forward_bytes(prof, N, L):
     return tot
 
 
+PROFILE = os.path.join(ROOT, "profiles", "k_chain_sched_C2_forward.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the persistent chain kernel from its committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source has
+    changed since those counters were taken (or there is no summary)."""
+    import hashlib
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        k, _, v = line.strip().partition(": ")
+        if k in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+            vals[k] = v.strip()
+    if len(vals) != 2:
+        return None
+    src = os.path.join(ROOT, "paper_2004_10908_amd", "csrc", "sdnn_fwd.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != vals["kernel_source_sha256"]:
+        return None
+    return int(vals["traffic_bytes_per_launch"])
+
+
 def live_edges(prof, N, L):
     return sum(int(prof[l]) for l in range(L)) * N * K
 
@@ -164,8 +189,11 @@ def main():
         kernel = "sdnn::k_layer_sched<512, 40> (one graph node per layer; step time / layers)"
         alg_launch, dur_ms = alg / L, ms / L
     achieved = alg_launch / (dur_ms / 1e3) / 1e9
+    tb = measured_traffic() if timed_kernel else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": round(tb / (dur_ms / 1e3) / 1e9, 1) if tb else None,
+                "traffic_bytes_per_launch": tb, "kernel": kernel,
                 "alg_bytes_per_launch": alg_launch, "avg_launch_ms": round(dur_ms, 4)}
     log(f"C2 {engine}: {ms:.3f} ms/step, {value:.3e} edges/s, profile head {prof[:5].tolist()}, nz {n_nz}")
 
