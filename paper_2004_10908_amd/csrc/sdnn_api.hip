@@ -74,7 +74,10 @@ int sched_parts(const sdnn_desc& d) { return ((d.n_neurons + 63) / 64 + 15) / 16
 bool sched_possible(const sdnn_desc& d) {
     const int nblk = (d.n_neurons + 63) / 64;
     const int G = (nblk + 15) / 16;
-    return d.n_neurons % 16 == 0 && sched_lds_bytes(d.n_neurons) <= LDS_BUDGET && (G == 1 || G == 2 || G == 4);
+    // the tile copies address a row as a 32-bit byte offset from the activation base
+    const bool offs32 = (int64_t)std::max<int64_t>(d.max_rows, 1) * d.n_neurons * 4 <= ((int64_t)1 << 32);
+    return d.n_neurons % 16 == 0 && sched_lds_bytes(d.n_neurons) <= LDS_BUDGET && (G == 1 || G == 2 || G == 4) &&
+           offs32;
 }
 
 Layout make_layout(const sdnn_desc& d) {
@@ -651,10 +654,10 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
             std::vector<int32_t> hln((size_t)L * npad), hws((size_t)L * n->nblk);
             const int worst = build_schedule(hidx.data(), N, L, SCHED_DSTORE, hent.data(), hln.data(), hws.data());
             if (worst <= SCHED_DSTORE) {
-                // the kernel wants byte offsets in the [id][row] compute tile: id -> 16 id
+                // the kernel wants LDS byte offsets in buffer 0: id -> 512 (id / 16) + 16 (id % 16)
                 for (auto& e : hent) {
                     const uint32_t id = (e >> 5) & 0x03ffffffu;
-                    e = (e & 0x8000001fu) | ((id << 4) << 5);
+                    e = (e & 0x8000001fu) | ((((id >> 4) << 9) | ((id & 15u) << 4)) << 5);
                 }
                 HIPCHK(hipMemcpyAsync(n->ent, hent.data(), hent.size() * 4, hipMemcpyHostToDevice, s));
                 HIPCHK(hipMemcpyAsync(n->lane_neuron, hln.data(), hln.size() * 4, hipMemcpyHostToDevice, s));
@@ -679,7 +682,7 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
                         const uint32_t e = tent[i] & 0x7fffffffu;
                         const uint32_t col = e / K;
                         tw[i] = e;
-                        tent[i] = (tent[i] & 0x80000000u) | ((col << 4) << 5);
+                        tent[i] = (tent[i] & 0x80000000u) | ((((col >> 4) << 9) | ((col & 15u) << 4)) << 5);
                     }
                     n->ent_t = (uint32_t*)(n->ws + lay.ent_t);
                     n->ent_w = (uint32_t*)(n->ws + lay.ent_w);

@@ -325,74 +325,53 @@ __global__ __launch_bounds__(NT) void k_chain(ChainArgs c) {
 // (b/(8G))*8 + b%8, so the parts of a tile run on the same XCD (blockIdx % 8)
 // and share its L2.
 //
-// LDS: the compute tile C, [id][row] (16 bytes per id, the 4 rows of one input:
-// one 16-byte read feeds 4 FMAs, and id's bank group is id mod 16), then the
-// landing area A, row-major (4 rows of N floats), then 128 bytes of scalars,
-// then the overflow area.  The rows of the next tile arrive in A with
-// asynchronous 16-byte-per-lane global->LDS copies (1 KB of one row per
-// instruction) while C is being read; at the top of a tile the workgroup
-// transposes A into C.
+// LDS: two tile buffers [id][row] (16 bytes per id, the 4 rows of one input: one
+// 16-byte read feeds 4 FMAs), interleaved in 256-byte blocks: block m (ids 16m ..
+// 16m+15) of buffer b at byte (2m + b) * 256, so an id's offset is
+// 512 (id / 16) + 16 (id % 16) in buffer 0 and the same + an immediate 256 in
+// buffer 1, and its bank group is id mod 16 in either.  Then 128 bytes of scalars,
+// the output staging area, the overflow area.  The next tile arrives in the other
+// buffer with asynchronous global->LDS copies while this one is being read.
 struct SchedLds {
-    float* C;             // [N][4]
-    float* A;             // [4][N]
     unsigned* scalars;    // 32 words
-    float* out;           // [4][SCHED_PART] outputs of the workgroup's part for one tile
-    uint32_t base;        // LDS byte address of C
-    uint32_t land;        // LDS byte address of A
+    float* out;           // [waves][4][128] each wave's outputs of one tile (its two blocks)
+    uint32_t base;        // LDS byte address of the tile buffers
     uint32_t ovf;         // LDS byte address of the overflow area
     int N;
     __device__ __forceinline__ SchedLds(float* lds, int n)
-        : C(lds), A(lds + 4 * n), scalars(reinterpret_cast<unsigned*>(lds + 8 * n)),
-          out(lds + 8 * n + SCHED_SCALARS / 4), base((uint32_t)(uintptr_t)lds),
-          land((uint32_t)(uintptr_t)lds + 16u * n),
-          ovf((uint32_t)(uintptr_t)lds + 32u * n + SCHED_SCALARS + SCHED_OUT), N(n) {}
-    // The copies of 4 rows of src into A come in 1 KB pieces (256 floats of one row);
-    // wave w issues pieces w, w + waves, ...  Row t's id is in lane t of `row`.
-    __device__ __forceinline__ int pieces(int wave, int waves) const {
-        const int total = SCHED_T * ((N + 255) >> 8);
+        : scalars(reinterpret_cast<unsigned*>(lds + 8 * n)), out(lds + 8 * n + SCHED_SCALARS / 4),
+          base((uint32_t)(uintptr_t)lds), ovf((uint32_t)(uintptr_t)lds + 32u * n + SCHED_SCALARS + SCHED_OUT), N(n) {}
+    // The copies of a tile's 4 rows into buffer `buf` come in chunks of 16 ids x 4 rows
+    // (256 bytes; lane l brings row l % 4 of id 16c + l / 4, so the chunk lands as
+    // [id][row]); wave w issues chunks w, w + waves, ...  `row` is the lane's row
+    // (tile row l % 4).  Scalar base (src + 16c floats) + 32-bit lane offset; the
+    // caller guarantees rows * N * 4 < 2^32.
+    __device__ __forceinline__ int chunks(int wave, int waves) const {
+        const int total = N >> 4;
         return wave < total ? (total - wave + waves - 1) / waves : 0;
     }
-    __device__ __forceinline__ void stage_piece(const float* src, int row, int wave, int lane, int waves, int i) const {
-        const int P = (N + 255) >> 8;
+    __device__ __forceinline__ void stage_chunk(const float* src, uint32_t voff, int wave, int waves, int i,
+                                                int buf) const {
         const int c = wave + i * waves;
-        const int r = c / P;
-        const int col = 256 * (c - r * P);
-        const int rid = __builtin_amdgcn_readlane(row, r);
-        if (col + 4 * lane < N) {
-            // scalar base (the piece's first float) + 16 bytes per lane: no per-lane 64-bit address
-            const uint64_t gb = (uint64_t)(uintptr_t)(src + (size_t)rid * N + col);
-            // (readfirstlane returns int: widen through uint32_t, never by sign extension)
-            const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)gb);
-            const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(gb >> 32));
-            const uint64_t sb = ((uint64_t)hi << 32) | (uint64_t)lo;
-            const uint32_t voff = 16u * (uint32_t)lane;
-            const uint32_t dst = __builtin_amdgcn_readfirstlane(land + 4u * (uint32_t)(r * N + col));
-            uint32_t saved;
-            __asm__ volatile(
-                "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %3\n\tglobal_load_lds_dwordx4 %1, %2\n\ts_mov_b32 m0, %0"
-                : "=&s"(saved) : "v"(voff), "s"(sb), "s"(dst) : "memory");
-        }
+        const uint64_t gb = (uint64_t)(uintptr_t)(src + 16 * (size_t)c);
+        // (readfirstlane returns int: widen through uint32_t, never by sign extension)
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)gb);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(gb >> 32));
+        const uint64_t sb = ((uint64_t)hi << 32) | (uint64_t)lo;
+        const uint32_t dst = __builtin_amdgcn_readfirstlane(base + 512u * (uint32_t)c + 256u * (uint32_t)buf);
+        uint32_t saved;
+        __asm__ volatile(
+            "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %3\n\tglobal_load_lds_dword %1, %2\n\ts_mov_b32 m0, %0"
+            : "=&s"(saved) : "v"(voff), "s"(sb), "s"(dst) : "memory");
     }
-    __device__ __forceinline__ void stage(const float* src, int row, int wave, int lane, int waves) const {
-        const int np = pieces(wave, waves);
-        for (int i = 0; i < np; ++i) stage_piece(src, row, wave, lane, waves, i);
+    // the lane's offset for row `row`: row * N + (lane >> 2) floats, in bytes
+    __device__ __forceinline__ uint32_t lane_off(int row, int lane) const {
+        return 4u * ((uint32_t)row * (uint32_t)N + (uint32_t)(lane >> 2));
     }
-    // A (row-major) -> C ([id][row]); the caller brackets it with barriers.  Eight ids
-    // per thread per round, all reads issued before the writes.
-    __device__ __forceinline__ void transpose(int tid, int nt) const {
-        for (int i0 = tid; i0 < N; i0 += 8 * nt) {
-            float4 v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int i = i0 + u * nt;
-                if (i < N) v[u] = make_float4(A[i], A[N + i], A[2 * N + i], A[3 * N + i]);
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int i = i0 + u * nt;
-                if (i < N) reinterpret_cast<float4*>(C)[i] = v[u];
-            }
-        }
+    __device__ __forceinline__ void stage(const float* src, int row, int wave, int lane, int waves, int buf) const {
+        const int nc = chunks(wave, waves);
+        const uint32_t voff = lane_off(row, lane);
+        for (int i = 0; i < nc; ++i) stage_chunk(src, voff, wave, waves, i, buf);
     }
 };
 
@@ -510,7 +489,7 @@ struct SchedNeuron {
 // hook(g) runs at the start of group g (for every g with 4g < D): the caller's way
 // of spreading memory instructions over the compute instead of issuing them in a
 // burst that fills the memory pipeline and blocks the waves at issue.
-template <int DMAX, typename Hook>
+template <int DMAX, int BUF, typename Hook>
 __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_base, int lane, const SchedNeuron<DMAX>& n,
                                             float (&acc)[SCHED_T], Hook&& hook) {
     // Steps in groups of 4; the reads of group g+1 are issued before the FMAs of
@@ -520,14 +499,14 @@ __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_bas
     const int D = n.D;
     float4 v[2][4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[0][u] = lds_read16(n.off[u]);
+    for (int u = 0; u < 4; ++u) v[0][u] = lds_read16(n.off[u] + BUF * 256);
 #pragma unroll
     for (int g = 0; g < DMAX / 4; ++g) {
         if (4 * g < D) {
             hook(g);
             if (g + 1 < DMAX / 4) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) v[(g + 1) & 1][u] = lds_read16(n.off[4 * (g + 1) + u]);
+                for (int u = 0; u < 4; ++u) v[(g + 1) & 1][u] = lds_read16(n.off[4 * (g + 1) + u] + BUF * 256);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -547,7 +526,7 @@ __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_bas
             for (int st = DMAX; st < D; ++st) {
                 const uint2 e = lds_read8(n.ovf + (uint32_t)(st - DMAX) * 512u + 8u * (uint32_t)lane);
                 const float w = __uint_as_float(e.y);
-                const float4 c = lds_read16(e.x);
+                const float4 c = lds_read16(e.x + BUF * 256);
                 acc[0] = fmaf(w, c.x, acc[0]);
                 acc[1] = fmaf(w, c.y, acc[1]);
                 acc[2] = fmaf(w, c.z, acc[2]);
@@ -557,7 +536,7 @@ __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_bas
             for (int st = DMAX; st < D; ++st) {
                 const uint32_t e = a.ent[(size_t)n.slot * SCHED_DSTORE + st];
                 const float w = n.weight_of(a, e, st);
-                const float4 c = lds_read16(lds_base + ((e >> 5) & 0x03ffffffu));
+                const float4 c = lds_read16(lds_base + ((e >> 5) & 0x03ffffffu) + BUF * 256);
                 acc[0] = fmaf(w, c.x, acc[0]);
                 acc[1] = fmaf(w, c.y, acc[1]);
                 acc[2] = fmaf(w, c.z, acc[2]);
@@ -584,7 +563,7 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
     constexpr int WAVES = NT / 64;
     const int N = a.N;
     const SchedLds L(lds, N);
-    unsigned* s_bits = L.scalars;                         // [2] row bits of the last two tiles
+    unsigned* s_bits = L.scalars;                         // [3] row bits of the last three tiles
     int* s_pin = reinterpret_cast<int*>(L.scalars) + 8;   // [2][4] input rows of coming tiles
     int* s_pout = reinterpret_cast<int*>(L.scalars) + 16; // [2][4] output rows (linear mode)
     int* s_prog = reinterpret_cast<int*>(L.scalars) + 24; // [4] the parts' progress words, a tile old
@@ -669,35 +648,35 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
         }
     };
 
-    if (tid == 0) { s_bits[0] = 0u; s_bits[1] = 0u; }
-    // tile q's ids: plain loads before anything is in flight; tile q + S's: the ring
-    int row_c, orow_c;                               // rows of the tile being computed next
-    {
-        const int pp = pos_of(q);
-        row_c = a.list_in ? a.list_in[pp] : a.row_base + pp;
-        orow_c = (LINEAR && a.rows_out) ? a.rows_out[pp] : row_c;
-    }
-    L.stage(a.yin, row_c, wave, lane, WAVES);
+    if (tid == 0) { s_bits[0] = 0u; s_bits[1] = 0u; s_bits[2] = 0u; }
+    // the ids of tiles q and q + S come through the ring too, so no register in the
+    // loop ever waits on a row-id load
+    prefetch(q, 0);
     if (q + S < ntiles) prefetch(q + S, 1);
+    __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
+    __syncthreads();
+    int row_c = in_row(q, 0), orow_c = out_row(q, 0);   // rows of the tile being computed next
+    L.stage(a.yin, row_c, wave, lane, WAVES, 0);
     int tile_p = -1, row_p = 0, orow_p = 0;          // the previous tile (outputs not yet stored)
-    const int part0 = p * SCHED_PART;                // first neuron of this part
-    const int width = min(SCHED_PART, N - part0);    // its neurons
-    // Outputs of the previous tile, from the staging tile: 16 bytes per lane per store,
-    // each wave's 256 floats within one row.  `mine` = this part's row bits: where a
-    // row's slice of this part is all zero and dead rows must be cleared in another
-    // buffer (yzero), the slice's zeros go there too, so a row that dies is cleared by
-    // its parts without waiting for the other parts.
-    auto store_tile = [&](unsigned mine) {
+    // Each wave stages its own outputs (its two blocks: neurons wbase .. wbase+127,
+    // 4 rows) in a private 2 KB of LDS and stores them with 16-byte stores after the
+    // next barrier; no other wave touches that area.  `mine` = this part's row bits:
+    // where a row's slice of this part is all zero and dead rows must be cleared in
+    // another buffer (yzero), the slice's zeros go there too, so a row that dies is
+    // cleared by its parts without waiting for the other parts.
+    const int wbase = p * SCHED_PART + 128 * wave;
+    float* wout = L.out + 512 * wave;
+    auto store_own = [&](unsigned mine) {
         const int nv = min(T, R - tile_p * T);
 #pragma unroll
-        for (int k = 0; k < T * SCHED_PART / 4 / NT; ++k) {
-            const int e = (k * NT + tid) * 4;
-            const int t = __builtin_amdgcn_readfirstlane(e / SCHED_PART);
-            const int col = e % SCHED_PART;
-            if (t < nv && col < width) {
-                const int ro = __builtin_amdgcn_readlane(LINEAR ? orow_p : row_p, t);
-                const size_t o = (size_t)ro * N + part0 + col;
-                const float4 v = *reinterpret_cast<const float4*>(L.out + e);
+        for (int k = 0; k < 2; ++k) {
+            const int e = (k * 64 + lane) * 4;
+            const int t = e >> 7;                    // rows 2k (lanes 0..31) and 2k + 1
+            const int col = e & 127;
+            const int ro = __shfl(LINEAR ? orow_p : row_p, t);
+            if (t < nv && wbase + col < N) {
+                const size_t o = (size_t)ro * N + wbase + col;
+                const float4 v = *reinterpret_cast<const float4*>(wout + e);
                 *reinterpret_cast<float4*>(a.yout + o) = v;
                 if (a.ycopy) *reinterpret_cast<float4*>(a.ycopy + o) = v;
                 if (!LINEAR && a.yzero && !((mine >> t) & 1u))
@@ -708,6 +687,7 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
     int it = 0;
     for (int tile = q; tile < ntiles; tile += S, ++it) {
         const int buf = it & 1;
+        const int slot = it % 3;                     // row-bit word of this tile
         __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
         if (prog_q && tid == 0) {
             __hip_atomic_store(prog_q + p, (int)(tag | (unsigned)it), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -727,16 +707,19 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
                 }
             }
         }
-        __syncthreads();                             // the tile has landed; the compute tile is free
-        if (tile_p >= 0) {
-            const unsigned mine = (live || a.yzero) ? s_bits[buf ^ 1] : 0xfu;
-            if (live && wave == 0) advance(tile_p, row_p, mine);   // before any store: nothing outstanding
-            store_tile(mine);
-        }
-        L.transpose(tid, NT);
-        __syncthreads();                             // compute tile ready; landing area free
-        if (tid == 0) s_bits[buf ^ 1] = 0u;          // every wave has read it
+        // The tile has landed in buffer buf; every wave is done with the other buffer
+        // (the previous tile), which the next tile's copies now fill.
+        __syncthreads();
+        // (register moves of loop-carried row ids first, while nothing is outstanding)
         const int row_now = row_c, orow_now = orow_c;
+        if (tile_p >= 0) {
+            const unsigned mine = (live || a.yzero) ? s_bits[(it + 2) % 3] : 0xfu;
+            if (live && wave == 0) advance(tile_p, row_p, mine);   // before any store: nothing outstanding
+            store_own(mine);
+        }
+        // the word of two tiles ago: read by every wave before this barrier, next
+        // written after the next one
+        if (tid == 0) s_bits[(it + 1) % 3] = 0u;
         const bool more = tile + S < ntiles;
         if (more) {
             // ring slot (it + 1) & 1 holds tile + S's ids (copied a tile ago, waited above)
@@ -745,28 +728,38 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
         }
         if (tile + 2 * S < ntiles) prefetch(tile + 2 * S, buf);
         if (prog_q && wave == 0 && lane < G) lds_copy4_coherent(prog_q + lane, s_prog + lane);
-        // the next tile's copies, spread over the first neuron's groups
-        const int np = more ? L.pieces(wave, WAVES) : 0;
+        // the next tile's copies, two per compute group
+        const int nc = more ? L.chunks(wave, WAVES) : 0;
+        const uint32_t voff = L.lane_off(row_c, lane);
+        int ci = 0;
+        auto issue2 = [&](int) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (ci < nc) L.stage_chunk(a.yin, voff, wave, WAVES, ci++, buf ^ 1);
+        };
         float acc0[T] = {0.f, 0.f, 0.f, 0.f}, acc1[T] = {0.f, 0.f, 0.f, 0.f};
-        sched_steps<DMAX>(a, L.base, lane, n0, acc0, [&](int g) {
-            if (g < np) L.stage_piece(a.yin, row_c, wave, lane, WAVES, g);
-        });
-        for (int i = min(np, (n0.D + 3) >> 2); i < np; ++i) L.stage_piece(a.yin, row_c, wave, lane, WAVES, i);
-        sched_steps<DMAX>(a, L.base, lane, n1, acc1, [](int) {});
+        if (buf == 0) {
+            sched_steps<DMAX, 0>(a, L.base, lane, n0, acc0, issue2);
+            sched_steps<DMAX, 0>(a, L.base, lane, n1, acc1, issue2);
+        } else {
+            sched_steps<DMAX, 1>(a, L.base, lane, n0, acc0, issue2);
+            sched_steps<DMAX, 1>(a, L.base, lane, n1, acc1, issue2);
+        }
+        while (ci < nc) L.stage_chunk(a.yin, voff, wave, WAVES, ci++, buf ^ 1);
         unsigned bits = 0u;
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             const float o0 = LINEAR ? acc0[t] : fminf(fmaxf(acc0[t] + n0.bj, 0.f), a.clamp);
             const float o1 = LINEAR ? acc1[t] : fminf(fmaxf(acc1[t] + n1.bj, 0.f), a.clamp);
-            if (n0.j >= 0) L.out[t * SCHED_PART + (n0.j - part0)] = o0;
-            if (n1.j >= 0) L.out[t * SCHED_PART + (n1.j - part0)] = o1;
+            if (n0.j >= 0) wout[t * 128 + (n0.j - wbase)] = o0;
+            if (n1.j >= 0) wout[t * 128 + (n1.j - wbase)] = o1;
             bits |= ((o0 != 0.f && n0.j >= 0) || (o1 != 0.f && n1.j >= 0)) ? (1u << t) : 0u;
         }
         if (live || (!LINEAR && a.yzero)) {
             // row bits of this part: its waves meet in LDS (read after the next barrier)
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o);
-            if (lane == 0 && bits) atomicOr(&s_bits[buf], bits);
+            if (lane == 0 && bits) atomicOr(&s_bits[slot], bits);
         }
         tile_p = tile;
         row_p = row_now;
@@ -775,7 +768,7 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
     // drain: the last tile's outputs and the rest of the liveness pipeline
     __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
     __syncthreads();
-    const unsigned mine_last = (live || a.yzero) ? s_bits[(it - 1) & 1] : 0xfu;
+    const unsigned mine_last = (live || a.yzero) ? s_bits[(it - 1) % 3] : 0xfu;
     if (live && wave == 0) {
         advance(tile_p, row_p, mine_last);
         __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
@@ -783,7 +776,7 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
         __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
         advance(-1, 0, 0u);
     }
-    store_tile(mine_last);
+    store_own(mine_last);
     __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
 }
 
@@ -925,14 +918,14 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
             }
     };
     if (q < ntiles) {
-        L.stage(a.y_in, row_of(q), wave, lane, WAVES);
+        L.stage(a.y_in, row_of(q), wave, lane, WAVES, 0);
         fetch(q);
     }
-    for (int tile = q; tile < ntiles; tile += S) {
+    int it = 0;
+    for (int tile = q; tile < ntiles; tile += S, ++it) {
+        const int buf = it & 1;
         __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
-        __syncthreads();
-        L.transpose(tid, NT);
-        __syncthreads();
+        __syncthreads();                             // tile in buffer buf; the other buffer is free
         // G of this tile from the values fetched a tile ago (before any copy is issued,
         // so reading them waits for nothing new)
         float g[2][T];
@@ -945,7 +938,7 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
                 if (tile * T + t < R && j[h] >= 0) a.g_out[(size_t)(tile * T + t) * N + j[h]] = g[h][t];
             }
         if (tile + S < ntiles) {
-            L.stage(a.y_in, row_of(tile + S), wave, lane, WAVES);
+            L.stage(a.y_in, row_of(tile + S), wave, lane, WAVES, buf ^ 1);
             fetch(tile + S);
         }
 #pragma unroll
@@ -953,7 +946,7 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
 #pragma unroll
             for (int st = 0; st < DMAX; ++st) {
                 if (st < D[h]) {
-                    const float4 v = lds_read16(off[h][st]);
+                    const float4 v = buf == 0 ? lds_read16(off[h][st]) : lds_read16(off[h][st] + 256);
                     float s = acc[h][st];
                     s = fmaf(g[h][0], v.x, s);
                     s = fmaf(g[h][1], v.y, s);
@@ -967,7 +960,7 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
                 for (int st = DMAX; st < D[h]; ++st) {
                     const uint32_t e = a.ent[(size_t)slot[h] * SCHED_DSTORE + st];
                     if (e & 0x80000000u) continue;
-                    const float4 v = lds_read16(L.base + ((e >> 5) & 0x03ffffffu));
+                    const float4 v = lds_read16(L.base + ((e >> 5) & 0x03ffffffu) + 256u * (uint32_t)buf);
                     float s = pw[e & 31u];
                     s = fmaf(g[h][0], v.x, s);
                     s = fmaf(g[h][1], v.y, s);
