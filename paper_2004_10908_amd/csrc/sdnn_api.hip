@@ -50,7 +50,7 @@ sdnn_status fail(sdnn_status st, const char* fmt, ...) {
 constexpr size_t ALIGN = 256;
 constexpr int P_GROUPS = 64;                    // backward row groups (dW partials)
 constexpr int NBAR = BAR_WORDS;
-constexpr size_t LDS_BUDGET = 152 * 1024;       // dynamic LDS a layer tile may use
+constexpr size_t LDS_BUDGET = 160 * 1024;       // dynamic LDS a workgroup may use (gfx950 maximum)
 constexpr int MSE_BLOCKS = 256;
 constexpr int SCHED_GRID = 256;                 // workgroups of the scheduled kernels (8 XCDs x 32)
 

@@ -889,11 +889,15 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
         }
 #pragma unroll
         for (int st = 0; st < DMAX; ++st) __asm__ volatile("" : "+v"(off[h][st]));
-        // this stream's partials start at zero (steps past DMAX accumulate in memory)
-        if (j[h] >= 0) {
+        // Every slot of a neuron appears once in its schedule, so the final write of the
+        // register sums covers the stream's partials; only slots of steps past DMAX,
+        // which accumulate in memory, start from zero here.
+        if (j[h] >= 0 && D[h] > DMAX) {
             float* pw = a.pdw + ((size_t)q * N + j[h]) * K;
-#pragma unroll
-            for (int k = 0; k < K; ++k) pw[k] = 0.f;
+            for (int st = DMAX; st < D[h]; ++st) {
+                const uint32_t e = a.ent[(size_t)slot[h] * SCHED_DSTORE + st];
+                if (!(e & 0x80000000u)) pw[e & 31u] = 0.f;
+            }
         }
     }
     // rows of a tile are consecutive (padding positions repeat the tile's first row)
@@ -943,16 +947,23 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
+            // groups of 4 steps, all reads of a group issued before its FMAs
 #pragma unroll
-            for (int st = 0; st < DMAX; ++st) {
-                if (st < D[h]) {
-                    const float4 v = buf == 0 ? lds_read16(off[h][st]) : lds_read16(off[h][st] + 256);
-                    float s = acc[h][st];
-                    s = fmaf(g[h][0], v.x, s);
-                    s = fmaf(g[h][1], v.y, s);
-                    s = fmaf(g[h][2], v.z, s);
-                    s = fmaf(g[h][3], v.w, s);
-                    acc[h][st] = s;
+            for (int g4 = 0; g4 < DMAX / 4; ++g4) {
+                if (4 * g4 < D[h]) {
+                    float4 v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        v[u] = buf == 0 ? lds_read16(off[h][4 * g4 + u]) : lds_read16(off[h][4 * g4 + u] + 256);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        float s = acc[h][4 * g4 + u];
+                        s = fmaf(g[h][0], v[u].x, s);
+                        s = fmaf(g[h][1], v[u].y, s);
+                        s = fmaf(g[h][2], v[u].z, s);
+                        s = fmaf(g[h][3], v[u].w, s);
+                        acc[h][4 * g4 + u] = s;
+                    }
                 }
             }
             if (D[h] > DMAX && j[h] >= 0) {
@@ -1080,8 +1091,8 @@ static const FwdVariant g_variants[] = {
 #undef SDNN_VD
 
 int fwd_variant_count() { return (int)(sizeof(g_variants) / sizeof(g_variants[0])); }
-const void* bwd_dw_sched_fn() { return (const void*)&k_bwd_dw_sched<SCHED_NT, SCHED_DMAX>; }
-const void* bwd_dy_sched_fn() { return (const void*)&k_bwd_dy_sched<SCHED_NT, SCHED_DMAX>; }
+const void* bwd_dw_sched_fn() { return (const void*)&k_bwd_dw_sched<SCHED_NT, SCHED_DMAX_T>; }
+const void* bwd_dy_sched_fn() { return (const void*)&k_bwd_dy_sched<SCHED_NT, SCHED_DMAX_T>; }
 const FwdVariant& fwd_variant(int i) { return g_variants[i]; }
 
 }  // namespace sdnn
