@@ -470,7 +470,7 @@ sdnn_status backward_layer_sched(const sdnn_net_s* n, int l, const float* y_in, 
                                  float* db_l, hipStream_t s) {
     const int N = n->d.n_neurons;
     const size_t npad = (size_t)n->nblk * 64;
-    const size_t sh = (size_t)2 * SCHED_T * N * 4 + SCHED_SCALARS;
+    const size_t sh = sched_lds_bytes(N);
     const int S = SCHED_GRID / n->parts;
     SchedDwArgs da{};
     da.y_in = y_in;
@@ -488,7 +488,7 @@ sdnn_status backward_layer_sched(const sdnn_net_s* n, int l, const float* y_in, 
     da.nblk = n->nblk;
     da.clamp = n->d.clamp;
     void* dargs[] = {&da};
-    HIPCHK(hipLaunchKernel(bwd_dw_sched_fn(), dim3(SCHED_GRID), dim3(SCHED_NT), dargs, sh, s));
+    HIPCHK(hipLaunchKernel(bwd_dw_sched_fn(), dim3(SCHED_GRID), dim3(2 * SCHED_NT), dargs, sh, s));
     hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for((int64_t)N * K + N)), dim3(256), 0, s, (const float*)n->pdw,
                        (const float*)n->pdb, (int32_t)S, (int32_t)N, dw_l, db_l);
     if (dy_in) {
@@ -694,8 +694,8 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
                     HIPCHK(hipMemcpyAsync(n->lane_input, tln.data(), tln.size() * 4, hipMemcpyHostToDevice, s));
                     HIPCHK(hipMemcpyAsync(n->steps_t, tws.data(), tws.size() * 4, hipMemcpyHostToDevice, s));
                     HIPCHK(hipStreamSynchronize(s));
-                    const size_t sh = (size_t)2 * SCHED_T * N * 4 + SCHED_SCALARS;
-                    HIPCHK(hipFuncSetAttribute(bwd_dw_sched_fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+                    HIPCHK(hipFuncSetAttribute(bwd_dw_sched_fn(), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                              (int)sched_lds_bytes(N)));
                     HIPCHK(hipFuncSetAttribute(bwd_dy_sched_fn(), hipFuncAttributeMaxDynamicSharedMemorySize,
                                               (int)sched_lds_bytes(N)));
                     n->sched_bwd = true;

@@ -840,20 +840,24 @@ __global__ __launch_bounds__(NT) void k_bwd_dy_sched(LayerArgs a) {
     run_layer_sched<NT, DMAX, true>(a, lds, R);
 }
 
-// Weight and bias gradients with the forward schedule.  Each lane owns two
-// neurons; for every step (one slot of its neuron) it keeps
+// Weight and bias gradients with the forward schedule.  A workgroup of 1024
+// lanes (16 waves, four per SIMD) owns a part of 1024 neurons; each lane owns one
+// neuron and, for every step (one slot of its neuron), keeps
 //   acc[st] = sum over its rows of G[r][j] * Y_l[r][id(st)]
 // (rows in ascending order within its tile stream), so a stream's partial sums
 // are deterministic.  The masked gradient G[r][j] = dY[r][j] [0 < Y_{l+1} < c]
-// of its neurons is also written out for the input-gradient pass.  Tiles of
-// Y_l are staged like the forward kernel's; the Y_{l+1} and dY values a lane
-// needs for a tile are loaded one tile ahead, into the registers the current
-// tile's values have just left.
+// is also written out for the input-gradient pass.  Tiles of Y_l are staged like
+// the forward kernel's (the next tile's copies spread over the compute groups);
+// the Y_{l+1} and dY values a lane needs for a tile are loaded one tile ahead.
+// Steps past DMAX keep their (offset, sum) pairs in the LDS overflow area (else
+// in memory).  With one neuron per lane the sums fit in 128 registers, so four
+// waves per SIMD hide the LDS latency.
 template <int NT, int DMAX>
 __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
     extern __shared__ __align__(16) float lds[];
     constexpr int T = SCHED_T;
     constexpr int WAVES = NT / 64;
+    static_assert(WAVES == 16, "one block of 64 neurons per wave, 16 blocks per part");
     const int N = a.N;
     const SchedLds L(lds, N);
     const int R = *a.nrows;
@@ -867,36 +871,45 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
     const int q = (kk / G) * 8 + x;
     const int S = (int)gridDim.x / G;
     const int ntiles = (R + T - 1) / T;
-    int j[2], D[2], slot[2];
-    uint32_t off[2][DMAX];
-    float acc[2][DMAX];
-    float accb[2] = {0.f, 0.f};
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int blk = p * 16 + 2 * wave + h;
-        const bool have = blk < a.nblk;
-        slot[h] = blk * 64 + lane;
-        j[h] = have ? a.lane_neuron[slot[h]] : -1;
-        D[h] = have ? __builtin_amdgcn_readfirstlane(a.wave_steps[blk]) : 0;
+    const int blk = p * 16 + wave;
+    const bool have = blk < a.nblk;
+    const int slot = blk * 64 + lane;
+    const int j = have ? a.lane_neuron[slot] : -1;
+    const int D = have ? __builtin_amdgcn_readfirstlane(a.wave_steps[blk]) : 0;
+    uint32_t off[DMAX];
+    float acc[DMAX];
+    float accb = 0.f;
+    {
         uint32_t e[DMAX];
 #pragma unroll
         for (int st = 0; st < DMAX; ++st)
-            e[st] = (have && st < D[h]) ? a.ent[(size_t)slot[h] * SCHED_DSTORE + st] : (0x80000000u | 31u);
+            e[st] = (have && st < D) ? a.ent[(size_t)slot * SCHED_DSTORE + st] : (0x80000000u | 31u);
 #pragma unroll
         for (int st = 0; st < DMAX; ++st) {
-            off[h][st] = L.base + ((e[st] >> 5) & 0x03ffffffu);
-            acc[h][st] = 0.f;
+            off[st] = L.base + ((e[st] >> 5) & 0x03ffffffu);
+            acc[st] = 0.f;
         }
+    }
 #pragma unroll
-        for (int st = 0; st < DMAX; ++st) __asm__ volatile("" : "+v"(off[h][st]));
-        // Every slot of a neuron appears once in its schedule, so the final write of the
-        // register sums covers the stream's partials; only slots of steps past DMAX,
-        // which accumulate in memory, start from zero here.
-        if (j[h] >= 0 && D[h] > DMAX) {
-            float* pw = a.pdw + ((size_t)q * N + j[h]) * K;
-            for (int st = DMAX; st < D[h]; ++st) {
-                const uint32_t e = a.ent[(size_t)slot[h] * SCHED_DSTORE + st];
-                if (!(e & 0x80000000u)) pw[e & 31u] = 0.f;
+    for (int st = 0; st < DMAX; ++st) __asm__ volatile("" : "+v"(off[st]));
+    uint32_t ovf = ~0u;            // LDS address of the block's overflow (offset, sum) pairs, or ~0u
+    if (D > DMAX) {
+        // the part's blocks take the overflow area in block order
+        int pre = 0;
+        for (int b2 = p * 16; b2 < blk; ++b2) pre += max(0, __builtin_amdgcn_readfirstlane(a.wave_steps[b2]) - DMAX);
+        if (pre + (D - DMAX) <= SCHED_OVF) {
+            ovf = L.ovf + (uint32_t)pre * 512u;
+            uint2* dst = reinterpret_cast<uint2*>(reinterpret_cast<char*>(lds) + (ovf - L.base)) + lane;
+            for (int st = DMAX; st < D; ++st) {
+                const uint32_t e2 = a.ent[(size_t)slot * SCHED_DSTORE + st];
+                dst[(st - DMAX) * 64] = make_uint2(L.base + ((e2 >> 5) & 0x03ffffffu), __float_as_uint(0.f));
+            }
+        } else if (j >= 0) {
+            // no room: those slots accumulate in memory, from zero
+            float* pw = a.pdw + ((size_t)q * N + j) * K;
+            for (int st = DMAX; st < D; ++st) {
+                const uint32_t e2 = a.ent[(size_t)slot * SCHED_DSTORE + st];
+                if (!(e2 & 0x80000000u)) pw[e2 & 31u] = 0.f;
             }
         }
     }
@@ -905,21 +918,19 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
         const int pos = tile * T + (lane & 3);
         return pos < R ? pos : tile * T;
     };
-    float yo[2][T], dv[2][T];      // Y_{l+1} and dY of the lane's neurons for the next tile
+    float yo[T], dv[T];            // Y_{l+1} and dY of the lane's neuron for the next tile
     auto fetch = [&](int tile) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int t = 0; t < T; ++t) {
-                const int r = tile * T + t;
-                yo[h][t] = 0.f;
-                dv[h][t] = 0.f;
-                if (r < R && j[h] >= 0) {
-                    const size_t o = (size_t)r * N + j[h];
-                    yo[h][t] = a.y_out[o];
-                    dv[h][t] = a.dy[o];
-                }
+        for (int t = 0; t < T; ++t) {
+            const int r = tile * T + t;
+            yo[t] = 0.f;
+            dv[t] = 0.f;
+            if (r < R && j >= 0) {
+                const size_t o = (size_t)r * N + j;
+                yo[t] = a.y_out[o];
+                dv[t] = a.dy[o];
             }
+        }
     };
     if (q < ntiles) {
         L.stage(a.y_in, row_of(q), wave, lane, WAVES, 0);
@@ -932,69 +943,87 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
         __syncthreads();                             // tile in buffer buf; the other buffer is free
         // G of this tile from the values fetched a tile ago (before any copy is issued,
         // so reading them waits for nothing new)
-        float g[2][T];
+        float g[T];
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int t = 0; t < T; ++t) {
-                g[h][t] = (yo[h][t] > 0.f && yo[h][t] < a.clamp) ? dv[h][t] : 0.f;
-                accb[h] += g[h][t];
-                if (tile * T + t < R && j[h] >= 0) a.g_out[(size_t)(tile * T + t) * N + j[h]] = g[h][t];
-            }
-        if (tile + S < ntiles) {
-            L.stage(a.y_in, row_of(tile + S), wave, lane, WAVES, buf ^ 1);
-            fetch(tile + S);
+        for (int t = 0; t < T; ++t) {
+            g[t] = (yo[t] > 0.f && yo[t] < a.clamp) ? dv[t] : 0.f;
+            accb += g[t];
+            if (tile * T + t < R && j >= 0) a.g_out[(size_t)(tile * T + t) * N + j] = g[t];
         }
+        const bool more = tile + S < ntiles;
+        if (more) fetch(tile + S);
+        // the next tile's copies, two per compute group
+        const int nc = more ? L.chunks(wave, WAVES) : 0;
+        const uint32_t voff = L.lane_off(row_of(tile + S), lane);
+        int ci = 0;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            // groups of 4 steps, all reads of a group issued before its FMAs
+        for (int g4 = 0; g4 < DMAX / 4; ++g4) {
+            if (4 * g4 < D) {
 #pragma unroll
-            for (int g4 = 0; g4 < DMAX / 4; ++g4) {
-                if (4 * g4 < D[h]) {
-                    float4 v[4];
+                for (int u = 0; u < 2; ++u)
+                    if (ci < nc) L.stage_chunk(a.y_in, voff, wave, WAVES, ci++, buf ^ 1);
+                float4 v[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        v[u] = buf == 0 ? lds_read16(off[h][4 * g4 + u]) : lds_read16(off[h][4 * g4 + u] + 256);
+                for (int u = 0; u < 4; ++u) v[u] = buf == 0 ? lds_read16(off[4 * g4 + u]) : lds_read16(off[4 * g4 + u] + 256);
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        float s = acc[h][4 * g4 + u];
-                        s = fmaf(g[h][0], v[u].x, s);
-                        s = fmaf(g[h][1], v[u].y, s);
-                        s = fmaf(g[h][2], v[u].z, s);
-                        s = fmaf(g[h][3], v[u].w, s);
-                        acc[h][4 * g4 + u] = s;
-                    }
+                for (int u = 0; u < 4; ++u) {
+                    float s = acc[4 * g4 + u];
+                    s = fmaf(g[0], v[u].x, s);
+                    s = fmaf(g[1], v[u].y, s);
+                    s = fmaf(g[2], v[u].z, s);
+                    s = fmaf(g[3], v[u].w, s);
+                    acc[4 * g4 + u] = s;
                 }
             }
-            if (D[h] > DMAX && j[h] >= 0) {
-                float* pw = a.pdw + ((size_t)q * N + j[h]) * K;
-                for (int st = DMAX; st < D[h]; ++st) {
-                    const uint32_t e = a.ent[(size_t)slot[h] * SCHED_DSTORE + st];
-                    if (e & 0x80000000u) continue;
-                    const float4 v = lds_read16(L.base + ((e >> 5) & 0x03ffffffu) + 256u * (uint32_t)buf);
-                    float s = pw[e & 31u];
-                    s = fmaf(g[h][0], v.x, s);
-                    s = fmaf(g[h][1], v.y, s);
-                    s = fmaf(g[h][2], v.z, s);
-                    s = fmaf(g[h][3], v.w, s);
-                    pw[e & 31u] = s;
+        }
+        while (ci < nc) L.stage_chunk(a.y_in, voff, wave, WAVES, ci++, buf ^ 1);
+        if (D > DMAX) {
+            if (ovf != ~0u) {
+                for (int st = DMAX; st < D; ++st) {
+                    const uint32_t pa = ovf + (uint32_t)(st - DMAX) * 512u + 8u * (uint32_t)lane;
+                    const uint2 e2 = lds_read8(pa);
+                    const float4 c = lds_read16(e2.x + 256u * (uint32_t)buf);
+                    float s = __uint_as_float(e2.y);
+                    s = fmaf(g[0], c.x, s);
+                    s = fmaf(g[1], c.y, s);
+                    s = fmaf(g[2], c.z, s);
+                    s = fmaf(g[3], c.w, s);
+                    reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + (pa - L.base))[1] = s;
+                }
+            } else if (j >= 0) {
+                float* pw = a.pdw + ((size_t)q * N + j) * K;
+                for (int st = DMAX; st < D; ++st) {
+                    const uint32_t e2 = a.ent[(size_t)slot * SCHED_DSTORE + st];
+                    if (e2 & 0x80000000u) continue;
+                    const float4 c = lds_read16(L.base + ((e2 >> 5) & 0x03ffffffu) + 256u * (uint32_t)buf);
+                    float s = pw[e2 & 31u];
+                    s = fmaf(g[0], c.x, s);
+                    s = fmaf(g[1], c.y, s);
+                    s = fmaf(g[2], c.z, s);
+                    s = fmaf(g[3], c.w, s);
+                    pw[e2 & 31u] = s;
                 }
             }
         }
     }
     __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        if (j[h] < 0) continue;
-        float* pw = a.pdw + ((size_t)q * N + j[h]) * K;
+    if (j >= 0) {
+        float* pw = a.pdw + ((size_t)q * N + j) * K;
 #pragma unroll
         for (int st = 0; st < DMAX; ++st) {
-            if (st < D[h]) {
-                const uint32_t e = a.ent[(size_t)slot[h] * SCHED_DSTORE + st];
-                if (!(e & 0x80000000u)) pw[e & 31u] = acc[h][st];
+            if (st < D) {
+                const uint32_t e2 = a.ent[(size_t)slot * SCHED_DSTORE + st];
+                if (!(e2 & 0x80000000u)) pw[e2 & 31u] = acc[st];
             }
         }
-        a.pdb[(size_t)q * N + j[h]] = accb[h];
+        if (ovf != ~0u) {
+            for (int st = DMAX; st < D; ++st) {
+                const uint32_t e2 = a.ent[(size_t)slot * SCHED_DSTORE + st];
+                const uint32_t pa = ovf + (uint32_t)(st - DMAX) * 512u + 8u * (uint32_t)lane;
+                if (!(e2 & 0x80000000u)) pw[e2 & 31u] = __uint_as_float(lds_read8(pa).y);
+            }
+        }
+        a.pdb[(size_t)q * N + j] = accb;
     }
 }
 
@@ -1091,7 +1120,7 @@ static const FwdVariant g_variants[] = {
 #undef SDNN_VD
 
 int fwd_variant_count() { return (int)(sizeof(g_variants) / sizeof(g_variants[0])); }
-const void* bwd_dw_sched_fn() { return (const void*)&k_bwd_dw_sched<SCHED_NT, SCHED_DMAX_T>; }
+const void* bwd_dw_sched_fn() { return (const void*)&k_bwd_dw_sched<2 * SCHED_NT, SCHED_DMAX>; }
 const void* bwd_dy_sched_fn() { return (const void*)&k_bwd_dy_sched<SCHED_NT, SCHED_DMAX_T>; }
 const FwdVariant& fwd_variant(int i) { return g_variants[i]; }
 
