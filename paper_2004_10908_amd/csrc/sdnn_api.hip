@@ -71,6 +71,16 @@ bool trainable(const sdnn_desc& d) { return (d.flags & SDNN_TRAINABLE) != 0; }
 // groups of 16, and at most 4 parts of 1024 neurons (grid of 256 = 8 XCDs x 32).
 int sched_parts(const sdnn_desc& d) { return ((d.n_neurons + 63) / 64 + 15) / 16; }
 
+// [L][npad][SCHED_DSTORE] (as the scheduler writes it) -> [L][SCHED_DSTORE][npad]
+void step_major(std::vector<uint32_t>& e, int L, size_t npad) {
+    std::vector<uint32_t> t(e.size());
+    for (int l = 0; l < L; ++l)
+        for (size_t sl = 0; sl < npad; ++sl)
+            for (int st = 0; st < SCHED_DSTORE; ++st)
+                t[((size_t)l * SCHED_DSTORE + st) * npad + sl] = e[((size_t)l * npad + sl) * SCHED_DSTORE + st];
+    e.swap(t);
+}
+
 bool sched_possible(const sdnn_desc& d) {
     const int nblk = (d.n_neurons + 63) / 64;
     const int G = (nblk + 15) / 16;
@@ -659,6 +669,9 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
                     const uint32_t id = (e >> 5) & 0x03ffffffu;
                     e = (e & 0x8000001fu) | ((((id >> 4) << 9) | ((id & 15u) << 4)) << 5);
                 }
+                // device layout is step-major per layer ([L][step][lane slot]): a wave's
+                // 64 lanes read one step's entries with one coalesced load
+                step_major(hent, L, npad);
                 HIPCHK(hipMemcpyAsync(n->ent, hent.data(), hent.size() * 4, hipMemcpyHostToDevice, s));
                 HIPCHK(hipMemcpyAsync(n->lane_neuron, hln.data(), hln.size() * 4, hipMemcpyHostToDevice, s));
                 HIPCHK(hipMemcpyAsync(n->wave_steps, hws.data(), hws.size() * 4, hipMemcpyHostToDevice, s));
@@ -689,6 +702,8 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
                     n->lane_input = (int32_t*)(n->ws + lay.lane_input);
                     n->steps_t = (int32_t*)(n->ws + lay.steps_t);
                     n->gbuf2 = (float*)(n->ws + lay.gbuf2);
+                    step_major(tent, L, npad);
+                    step_major(tw, L, npad);
                     HIPCHK(hipMemcpyAsync(n->ent_t, tent.data(), tent.size() * 4, hipMemcpyHostToDevice, s));
                     HIPCHK(hipMemcpyAsync(n->ent_w, tw.data(), tw.size() * 4, hipMemcpyHostToDevice, s));
                     HIPCHK(hipMemcpyAsync(n->lane_input, tln.data(), tln.size() * 4, hipMemcpyHostToDevice, s));

@@ -445,7 +445,7 @@ struct SchedNeuron {
     uint32_t ovf;   // LDS byte address of this block's overflow pairs (64 lanes x 8 bytes per step), or ~0u
     __device__ __forceinline__ float weight_of(const LayerArgs& a, uint32_t e, int st) const {
         const bool pad = (e & 0x80000000u) || j < 0;
-        return pad ? 0.f : (a.ent_w ? a.w[a.ent_w[(size_t)slot * SCHED_DSTORE + st]] : a.w[(size_t)j * K + (e & 31u)]);
+        return pad ? 0.f : (a.ent_w ? a.w[a.ent_w[(size_t)st * (a.nblk * 64) + slot]] : a.w[(size_t)j * K + (e & 31u)]);
     }
     __device__ __forceinline__ void load(const LayerArgs& a, int first_blk, int blk, int lane, uint32_t lds_base,
                                          uint32_t ovf_base, float* lds) {
@@ -458,7 +458,7 @@ struct SchedNeuron {
         uint32_t e[DMAX];
 #pragma unroll
         for (int st = 0; st < DMAX; ++st)
-            e[st] = (have && st < D) ? a.ent[(size_t)slot * SCHED_DSTORE + st] : (0x80000000u | 31u);
+            e[st] = (have && st < D) ? a.ent[(size_t)st * (a.nblk * 64) + slot] : (0x80000000u | 31u);
 #pragma unroll
         for (int st = 0; st < DMAX; ++st) {
             off[st] = lds_base + ((e[st] >> 5) & 0x03ffffffu);
@@ -475,7 +475,7 @@ struct SchedNeuron {
                 ovf = ovf_base + (uint32_t)pre * 512u;
                 uint2* dst = reinterpret_cast<uint2*>(reinterpret_cast<char*>(lds) + (ovf - lds_base)) + lane;
                 for (int st = DMAX; st < D; ++st) {
-                    const uint32_t x = a.ent[(size_t)slot * SCHED_DSTORE + st];
+                    const uint32_t x = a.ent[(size_t)st * (a.nblk * 64) + slot];
                     dst[(st - DMAX) * 64] =
                         make_uint2(lds_base + ((x >> 5) & 0x03ffffffu), __float_as_uint(weight_of(a, x, st)));
                 }
@@ -534,7 +534,7 @@ __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_bas
             }
         } else {
             for (int st = DMAX; st < D; ++st) {
-                const uint32_t e = a.ent[(size_t)n.slot * SCHED_DSTORE + st];
+                const uint32_t e = a.ent[(size_t)st * (a.nblk * 64) + n.slot];
                 const float w = n.weight_of(a, e, st);
                 const float4 c = lds_read16(lds_base + ((e >> 5) & 0x03ffffffu) + BUF * 256);
                 acc[0] = fmaf(w, c.x, acc[0]);
@@ -883,7 +883,7 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
         uint32_t e[DMAX];
 #pragma unroll
         for (int st = 0; st < DMAX; ++st)
-            e[st] = (have && st < D) ? a.ent[(size_t)slot * SCHED_DSTORE + st] : (0x80000000u | 31u);
+            e[st] = (have && st < D) ? a.ent[(size_t)st * (a.nblk * 64) + slot] : (0x80000000u | 31u);
 #pragma unroll
         for (int st = 0; st < DMAX; ++st) {
             off[st] = L.base + ((e[st] >> 5) & 0x03ffffffu);
@@ -901,14 +901,14 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
             ovf = L.ovf + (uint32_t)pre * 512u;
             uint2* dst = reinterpret_cast<uint2*>(reinterpret_cast<char*>(lds) + (ovf - L.base)) + lane;
             for (int st = DMAX; st < D; ++st) {
-                const uint32_t e2 = a.ent[(size_t)slot * SCHED_DSTORE + st];
+                const uint32_t e2 = a.ent[(size_t)st * (a.nblk * 64) + slot];
                 dst[(st - DMAX) * 64] = make_uint2(L.base + ((e2 >> 5) & 0x03ffffffu), __float_as_uint(0.f));
             }
         } else if (j >= 0) {
             // no room: those slots accumulate in memory, from zero
             float* pw = a.pdw + ((size_t)q * N + j) * K;
             for (int st = DMAX; st < D; ++st) {
-                const uint32_t e2 = a.ent[(size_t)slot * SCHED_DSTORE + st];
+                const uint32_t e2 = a.ent[(size_t)st * (a.nblk * 64) + slot];
                 if (!(e2 & 0x80000000u)) pw[e2 & 31u] = 0.f;
             }
         }
@@ -993,7 +993,7 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
             } else if (j >= 0) {
                 float* pw = a.pdw + ((size_t)q * N + j) * K;
                 for (int st = DMAX; st < D; ++st) {
-                    const uint32_t e2 = a.ent[(size_t)slot * SCHED_DSTORE + st];
+                    const uint32_t e2 = a.ent[(size_t)st * (a.nblk * 64) + slot];
                     if (e2 & 0x80000000u) continue;
                     const float4 c = lds_read16(L.base + ((e2 >> 5) & 0x03ffffffu) + 256u * (uint32_t)buf);
                     float s = pw[e2 & 31u];
@@ -1007,20 +1007,59 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
         }
     }
     __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
-    if (j >= 0) {
-        float* pw = a.pdw + ((size_t)q * N + j) * K;
+    // Partials out.  A wave's 64 neurons are one contiguous block of 64 rows of 32 floats
+    // in this stream's partials: staged in the wave's 1 KB of the output staging area in
+    // 8 rounds of 8 neurons, they go out as contiguous 16-byte stores instead of scattered
+    // 4-byte ones.  A block whose overflow sums live in memory writes its sums directly.
+    // The entry pointer walks one step at a time behind an empty asm, so that the
+    // compiler keeps one address instead of one 64-bit address per step.
+    const bool direct = D > DMAX && ovf == ~0u;
+    const int bbase = blk * 64;                    // first neuron of the block
+    const int jl = j - bbase;                      // the block holds neurons bbase..bbase+63
+    float* stg = L.out + 256 * wave;               // [8][32]
+    const size_t es = (size_t)a.nblk * 64;         // step stride of the schedule entries
+#pragma unroll 1
+    for (int r = 0; r < 8; ++r) {
+        __syncthreads();
+        if (!direct && j >= 0 && (jl >> 3) == r) {
+            const uint32_t* ep = a.ent + slot;
 #pragma unroll
-        for (int st = 0; st < DMAX; ++st) {
-            if (st < D) {
-                const uint32_t e2 = a.ent[(size_t)slot * SCHED_DSTORE + st];
-                if (!(e2 & 0x80000000u)) pw[e2 & 31u] = acc[st];
+            for (int st = 0; st < DMAX; ++st) {
+                if (st < D) {
+                    const uint32_t e2 = *ep;
+                    if (!(e2 & 0x80000000u)) stg[(jl & 7) * 32 + (e2 & 31u)] = acc[st];
+                }
+                ep += es;
+                __asm__ volatile("" : "+v"(ep));
+            }
+            if (ovf != ~0u) {
+                for (int st = DMAX; st < D; ++st) {
+                    const uint32_t e2 = *ep;
+                    const uint32_t pa = ovf + (uint32_t)(st - DMAX) * 512u + 8u * (uint32_t)lane;
+                    if (!(e2 & 0x80000000u)) stg[(jl & 7) * 32 + (e2 & 31u)] = __uint_as_float(lds_read8(pa).y);
+                    ep += es;
+                }
             }
         }
-        if (ovf != ~0u) {
-            for (int st = DMAX; st < D; ++st) {
-                const uint32_t e2 = a.ent[(size_t)slot * SCHED_DSTORE + st];
-                const uint32_t pa = ovf + (uint32_t)(st - DMAX) * 512u + 8u * (uint32_t)lane;
-                if (!(e2 & 0x80000000u)) pw[e2 & 31u] = __uint_as_float(lds_read8(pa).y);
+        __syncthreads();
+        // 8 neurons x 32 floats, one float4 per lane
+        const int nr = bbase + 8 * r + (lane >> 3);
+        if (!direct && have && nr < N)
+            *reinterpret_cast<float4*>(a.pdw + ((size_t)q * N + nr) * K + 4 * (lane & 7)) =
+                *reinterpret_cast<const float4*>(stg + 4 * lane);
+    }
+    if (j >= 0) {
+        if (direct) {
+            float* pw = a.pdw + ((size_t)q * N + j) * K;
+            const uint32_t* ep = a.ent + slot;
+#pragma unroll
+            for (int st = 0; st < DMAX; ++st) {
+                if (st < D) {
+                    const uint32_t e2 = *ep;
+                    if (!(e2 & 0x80000000u)) pw[e2 & 31u] = acc[st];
+                }
+                ep += es;
+                __asm__ volatile("" : "+v"(ep));
             }
         }
         a.pdb[(size_t)q * N + j] = accb;

@@ -34,7 +34,7 @@ struct LayerArgs {
     int32_t layer;
     float clamp;
     // scheduled (resident-weight) kernel only; ignored by the others
-    const uint32_t* ent;         // [npad][SCHED_DSTORE] slot schedule of this layer
+    const uint32_t* ent;         // [SCHED_DSTORE][npad] slot schedule of this layer (step-major: coalesced)
     const int32_t* lane_neuron;  // [npad] neuron of each lane slot (-1: none)
     const int32_t* wave_steps;   // [nblk] steps of each 64-neuron block
     int32_t* tile_bits;          // [max tiles] (parts done << 16) | per-part row bits, zero between layers
@@ -104,7 +104,7 @@ struct ChainArgs {
     int32_t compaction;
     float clamp;
     // scheduled kernel only (stacked over layers)
-    const uint32_t* ent;         // [L][npad][SCHED_DSTORE]
+    const uint32_t* ent;         // [L][SCHED_DSTORE][npad]
     const int32_t* lane_neuron;  // [L][npad]
     const int32_t* wave_steps;   // [L][nblk]
     int32_t* tile_bits;
