@@ -447,8 +447,10 @@ struct SchedNeuron {
         const bool pad = (e & 0x80000000u) || j < 0;
         return pad ? 0.f : (a.ent_w ? a.w[a.ent_w[(size_t)st * (a.nblk * 64) + slot]] : a.w[(size_t)j * K + (e & 31u)]);
     }
+    // d_even / d_odd: register steps of the part's even / odd blocks (for the
+    // overflow area's block order)
     __device__ __forceinline__ void load(const LayerArgs& a, int first_blk, int blk, int lane, uint32_t lds_base,
-                                         uint32_t ovf_base, float* lds) {
+                                         uint32_t ovf_base, float* lds, int d_even, int d_odd) {
         const bool have = blk < a.nblk;
         slot = blk * 64 + lane;
         j = have ? a.lane_neuron[slot] : -1;
@@ -470,7 +472,7 @@ struct SchedNeuron {
             // the part's blocks take the overflow area in block order
             int pre = 0;
             for (int b2 = first_blk; b2 < blk; ++b2)
-                pre += max(0, __builtin_amdgcn_readfirstlane(a.wave_steps[b2]) - DMAX);
+                pre += max(0, __builtin_amdgcn_readfirstlane(a.wave_steps[b2]) - (((b2 - first_blk) & 1) ? d_odd : d_even));
             if (pre + (D - DMAX) <= SCHED_OVF) {
                 ovf = ovf_base + (uint32_t)pre * 512u;
                 uint2* dst = reinterpret_cast<uint2*>(reinterpret_cast<char*>(lds) + (ovf - lds_base)) + lane;
@@ -523,14 +525,25 @@ __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_bas
         // the LDS and memory forms are separate loops so that the LDS one never waits
         // on outstanding memory operations (the staging of the next tile)
         if (n.ovf != ~0u) {
-            for (int st = DMAX; st < D; ++st) {
-                const uint2 e = lds_read8(n.ovf + (uint32_t)(st - DMAX) * 512u + 8u * (uint32_t)lane);
-                const float w = __uint_as_float(e.y);
-                const float4 c = lds_read16(e.x + BUF * 256);
-                acc[0] = fmaf(w, c.x, acc[0]);
-                acc[1] = fmaf(w, c.y, acc[1]);
-                acc[2] = fmaf(w, c.z, acc[2]);
-                acc[3] = fmaf(w, c.w, acc[3]);
+            // four steps at a time: their pairs, then their slots, then the FMAs (two
+            // LDS latencies per four steps); a group's steps past D re-read the last
+            // pair and add nothing
+            for (int st0 = DMAX; st0 < D; st0 += 4) {
+                uint2 e[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    e[u] = lds_read8(n.ovf + (uint32_t)(min(st0 + u, D - 1) - DMAX) * 512u + 8u * (uint32_t)lane);
+                float4 c[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) c[u] = lds_read16(e[u].x + BUF * 256);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float w = st0 + u < D ? __uint_as_float(e[u].y) : 0.f;
+                    acc[0] = fmaf(w, c[u].x, acc[0]);
+                    acc[1] = fmaf(w, c[u].y, acc[1]);
+                    acc[2] = fmaf(w, c[u].z, acc[2]);
+                    acc[3] = fmaf(w, c[u].w, acc[3]);
+                }
             }
         } else {
             for (int st = DMAX; st < D; ++st) {
@@ -557,7 +570,7 @@ __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_bas
 // the sum is read at tile t+2 (alive flags, zeroing of dead rows, list slot
 // reservation), the list entries are written at tile t+3, and whatever is left
 // drains after the last tile.
-template <int NT, int DMAX, bool LINEAR = false>
+template <int NT, int DMAX, bool LINEAR = false, int DMAX1 = DMAX>
 __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __restrict__ lds, int R) {
     constexpr int T = SCHED_T;
     constexpr int WAVES = NT / 64;
@@ -579,9 +592,11 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
     const int ntiles = (R + T - 1) / T;
     if (q >= ntiles) return;                         // uniform over the workgroup
     // a part is 16 blocks of 64 neurons; wave w owns blocks 2w and 2w + 1 of it
-    SchedNeuron<DMAX> n0, n1;
-    n0.load(a, p * 16, p * 16 + 2 * wave, lane, L.base, L.ovf, lds);
-    n1.load(a, p * 16, p * 16 + 2 * wave + 1, lane, L.base, L.ovf, lds);
+    // (DMAX register steps for the even block, DMAX1 for the odd one)
+    SchedNeuron<DMAX> n0;
+    SchedNeuron<DMAX1> n1;
+    n0.load(a, p * 16, p * 16 + 2 * wave, lane, L.base, L.ovf, lds, DMAX, DMAX1);
+    n1.load(a, p * 16, p * 16 + 2 * wave + 1, lane, L.base, L.ovf, lds, DMAX, DMAX1);
     const bool live = !LINEAR && (a.list_out || a.alive);
     int* prog_q = (G > 1 && a.prog) ? a.prog + 4 * q : nullptr;   // this stream's progress words
     const unsigned tag = ((unsigned)a.layer & 0xfffu) << 20;
@@ -740,10 +755,10 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
         float acc0[T] = {0.f, 0.f, 0.f, 0.f}, acc1[T] = {0.f, 0.f, 0.f, 0.f};
         if (buf == 0) {
             sched_steps<DMAX, 0>(a, L.base, lane, n0, acc0, issue2);
-            sched_steps<DMAX, 0>(a, L.base, lane, n1, acc1, issue2);
+            sched_steps<DMAX1, 0>(a, L.base, lane, n1, acc1, issue2);
         } else {
             sched_steps<DMAX, 1>(a, L.base, lane, n0, acc0, issue2);
-            sched_steps<DMAX, 1>(a, L.base, lane, n1, acc1, issue2);
+            sched_steps<DMAX1, 1>(a, L.base, lane, n1, acc1, issue2);
         }
         while (ci < nc) L.stage_chunk(a.yin, voff, wave, WAVES, ci++, buf ^ 1);
         unsigned bits = 0u;
@@ -833,11 +848,11 @@ __global__ __launch_bounds__(NT) void k_chain_sched(ChainArgs c) {
 // Input gradient through the transposed pattern: the scheduled kernel in linear
 // mode (lane = input neuron, steps = its incoming edges, tile = the masked
 // gradient G of 4 rows, no bias / clamp / liveness).
-template <int NT, int DMAX>
+template <int NT, int DMAX0, int DMAX1>
 __global__ __launch_bounds__(NT) void k_bwd_dy_sched(LayerArgs a) {
     extern __shared__ __align__(16) float lds[];
     const int R = a.cnt_in ? *a.cnt_in : a.nrows;
-    run_layer_sched<NT, DMAX, true>(a, lds, R);
+    run_layer_sched<NT, DMAX0, true, DMAX1>(a, lds, R);
 }
 
 // Weight and bias gradients with the forward schedule.  A workgroup of 1024
@@ -1160,7 +1175,7 @@ static const FwdVariant g_variants[] = {
 
 int fwd_variant_count() { return (int)(sizeof(g_variants) / sizeof(g_variants[0])); }
 const void* bwd_dw_sched_fn() { return (const void*)&k_bwd_dw_sched<2 * SCHED_NT, SCHED_DMAX>; }
-const void* bwd_dy_sched_fn() { return (const void*)&k_bwd_dy_sched<SCHED_NT, SCHED_DMAX_T>; }
+const void* bwd_dy_sched_fn() { return (const void*)&k_bwd_dy_sched<SCHED_NT, SCHED_DMAX_T0, SCHED_DMAX_T1>; }
 const FwdVariant& fwd_variant(int i) { return g_variants[i]; }
 
 }  // namespace sdnn

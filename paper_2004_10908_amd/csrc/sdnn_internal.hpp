@@ -69,7 +69,10 @@ constexpr int SCHED_T = 4;       // rows per tile of the scheduled kernel
 constexpr int SCHED_NT = 512;    // its workgroup size (each lane owns two neurons)
 constexpr int SCHED_DMAX = 40;   // schedule steps held in registers
 constexpr int SCHED_DSTORE = 64; // schedule steps stored per lane
-constexpr int SCHED_DMAX_T = 44;  // register steps of the backward kernels (the transposed schedule's in-degrees vary)
+// register steps of the input-gradient kernel's two blocks per wave: the transposed
+// schedule puts a wave's 64 highest-degree input neurons in its even block
+constexpr int SCHED_DMAX_T0 = 52;
+constexpr int SCHED_DMAX_T1 = 36;
 constexpr int SCHED_OVF = 30;    // block-steps past SCHED_DMAX a workgroup keeps in LDS (512 bytes each)
 constexpr int SCHED_SCALARS = 128; // bytes of per-workgroup scalars after the tile buffers
 constexpr int SCHED_PROG = 1024;   // ints of the parts' progress words ([streams][4])

@@ -235,7 +235,12 @@ int build_schedule_range(const int32_t* idx, int N, int l0, int l1, int dmax, ui
 
 // Transposed schedule of layers [l0, l1) (for the input-gradient gather): lane
 // slots are input neurons i, items are the edges (j, k) with idx[j][k] = i, read
-// from the gradient tile at column j (bank group j mod 16).
+// from the gradient tile at column j (bank group j mod 16).  Out-degrees vary
+// (about 32 +- 6 for uniform patterns) and a block takes as many steps as its
+// busiest lane, so the two blocks of a wave (neurons 128m .. 128m + 127) are
+// formed by degree: the even block takes the 64 highest-degree neurons, the odd
+// block the rest.  Both stay within the wave's 128 neurons, so the kernel's
+// per-wave output staging is unchanged.
 //   ent[...] = edge position j*K + k, or padding (bit 31 set, j*K = free group * K)
 int build_transposed_range(const int32_t* idx, int N, int l0, int l1, int dmax, uint32_t* ent, int32_t* lane_input,
                            int32_t* wave_steps) {
@@ -245,24 +250,34 @@ int build_transposed_range(const int32_t* idx, int N, int l0, int l1, int dmax, 
     std::array<std::vector<Item>, 64> lists;
     std::array<int, 64> member;
     std::array<std::vector<uint32_t>, 64> seq;
+    std::vector<int> order;
     for (int l = l0; l < l1; ++l) {
         const int32_t* il = idx + (size_t)l * N * K;
         for (auto& v : in_edges) v.clear();
         for (int j = 0; j < N; ++j)
             for (int k = 0; k < K; ++k) in_edges[il[(size_t)j * K + k]].push_back((uint32_t)(j * K + k));
         for (int b = 0; b < nblk; ++b) {
-            const int n = std::min(64, N - 64 * b);
+            if ((b & 1) == 0) {
+                // neurons of the block pair, by degree (descending; ties by id)
+                const int lo = 64 * b, hi = std::min(N, 64 * b + 128);
+                order.clear();
+                for (int i = lo; i < hi; ++i) order.push_back(i);
+                std::stable_sort(order.begin(), order.end(),
+                                 [&](int x, int y) { return in_edges[x].size() > in_edges[y].size(); });
+            }
+            const int first = (b & 1) ? 64 : 0;
+            const int n = std::max(0, std::min(64, (int)order.size() - first));
             for (int i = 0; i < 64; ++i) {
                 lists[i].clear();
                 if (i >= n) continue;
-                for (uint32_t e : in_edges[64 * b + i]) lists[i].push_back({(int)((e / K) % NG), e});
+                for (uint32_t e : in_edges[order[first + i]]) lists[i].push_back({(int)((e / K) % NG), e});
             }
             const int steps = schedule_block(lists, n, member, seq);
             worst = std::max(worst, steps);
             wave_steps[(size_t)l * nblk + b] = steps;
             for (int lane = 0; lane < 64; ++lane) {
                 const size_t slot = (size_t)l * npad + 64 * b + lane;
-                lane_input[slot] = member[lane] < n ? 64 * b + member[lane] : -1;
+                lane_input[slot] = member[lane] < n ? order[first + member[lane]] : -1;
                 for (int s = 0; s < dmax; ++s) {
                     uint32_t e = 0x80000000u;
                     if (s < (int)seq[lane].size()) {
