@@ -664,10 +664,10 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
             std::vector<int32_t> hln((size_t)L * npad), hws((size_t)L * n->nblk);
             const int worst = build_schedule(hidx.data(), N, L, SCHED_DSTORE, hent.data(), hln.data(), hws.data());
             if (worst <= SCHED_DSTORE) {
-                // the kernel wants LDS byte offsets in buffer 0: id -> 512 (id / 16) + 16 (id % 16)
+                // the kernel wants LDS byte offsets in buffer 0: id -> 2048 (id / 64) + 16 (id % 64)
                 for (auto& e : hent) {
                     const uint32_t id = (e >> 5) & 0x03ffffffu;
-                    e = (e & 0x8000001fu) | ((((id >> 4) << 9) | ((id & 15u) << 4)) << 5);
+                    e = (e & 0x8000001fu) | (sched_slot_offset(id) << 5);
                 }
                 // device layout is step-major per layer ([L][step][lane slot]): a wave's
                 // 64 lanes read one step's entries with one coalesced load
@@ -695,7 +695,7 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
                         const uint32_t e = tent[i] & 0x7fffffffu;
                         const uint32_t col = e / K;
                         tw[i] = e;
-                        tent[i] = (tent[i] & 0x80000000u) | ((((col >> 4) << 9) | ((col & 15u) << 4)) << 5);
+                        tent[i] = (tent[i] & 0x80000000u) | (sched_slot_offset(col) << 5);
                     }
                     n->ent_t = (uint32_t*)(n->ws + lay.ent_t);
                     n->ent_w = (uint32_t*)(n->ws + lay.ent_w);

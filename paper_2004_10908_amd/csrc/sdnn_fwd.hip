@@ -311,6 +311,55 @@ __global__ __launch_bounds__(NT) void k_chain(ChainArgs c) {
     // the nz list and the row profile are produced by a k_finalize launch after this kernel
 }
 
+// 16-byte LDS read at an absolute LDS byte address (the offsets already include
+// the workgroup's LDS base), so the address register is used as is.
+__device__ __forceinline__ float4 lds_read16(uint32_t addr) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    __builtin_assume((addr & 15u) == 0u);
+    const v4f r = *reinterpret_cast<const v4f __attribute__((address_space(3)))*>(addr);
+    return make_float4(r.x, r.y, r.z, r.w);
+#else
+    (void)addr;   // host pass of a device-only function
+    return make_float4(0.f, 0.f, 0.f, 0.f);
+#endif
+}
+
+// 4-byte LDS read and 16-byte LDS write at absolute LDS byte addresses.
+__device__ __forceinline__ float lds_read4(uint32_t addr) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_assume((addr & 3u) == 0u);
+    return *reinterpret_cast<const float __attribute__((address_space(3)))*>(addr);
+#else
+    (void)addr;
+    return 0.f;
+#endif
+}
+__device__ __forceinline__ void lds_write16(uint32_t addr, float4 v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    __builtin_assume((addr & 15u) == 0u);
+    v4f r = {v.x, v.y, v.z, v.w};
+    *reinterpret_cast<v4f __attribute__((address_space(3)))*>(addr) = r;
+#else
+    (void)addr;
+    (void)v;
+#endif
+}
+
+// 8-byte LDS read at an absolute LDS byte address.
+__device__ __forceinline__ uint2 lds_read8(uint32_t addr) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef unsigned v2u __attribute__((ext_vector_type(2)));
+    __builtin_assume((addr & 7u) == 0u);
+    const v2u r = *reinterpret_cast<const v2u __attribute__((address_space(3)))*>(addr);
+    return make_uint2(r.x, r.y);
+#else
+    (void)addr;
+    return make_uint2(0u, 0u);
+#endif
+}
+
 // ---------------------------------------------------------------- scheduled kernel
 // Resident-weight variant for layers whose 4-row tile fits LDS twice
 // (N <= 4096 or so).  A workgroup of 512 lanes owns 1024 neurons ("part") for the
@@ -326,12 +375,20 @@ __global__ __launch_bounds__(NT) void k_chain(ChainArgs c) {
 // and share its L2.
 //
 // LDS: two tile buffers [id][row] (16 bytes per id, the 4 rows of one input: one
-// 16-byte read feeds 4 FMAs), interleaved in 256-byte blocks: block m (ids 16m ..
-// 16m+15) of buffer b at byte (2m + b) * 256, so an id's offset is
-// 512 (id / 16) + 16 (id % 16) in buffer 0 and the same + an immediate 256 in
+// 16-byte read feeds 4 FMAs) in blocks of 64 ids, the blocks of the two buffers
+// interleaved: block m of buffer b at byte 2048 m + 1024 b, so an id's offset is
+// 2048 (id / 64) + 16 (id % 64) in buffer 0 and the same + an immediate 1024 in
 // buffer 1, and its bank group is id mod 16 in either.  Then 128 bytes of scalars,
-// the output staging area, the overflow area.  The next tile arrives in the other
-// buffer with asynchronous global->LDS copies while this one is being read.
+// the output staging area, the overflow area.
+//
+// The next tile arrives in the other buffer with asynchronous 16-byte global->LDS
+// copies while this one is being read.  A copy lands its 64 lanes' 16 bytes in lane
+// order, so one copy of block m brings rows 0..3 of ids 64m .. 64m+63 as [row][id]
+// (lane l: row l / 16, ids 64m + 4 (l % 16) .. +3); the wave that issued it turns
+// the block into [id][row] in place once it has landed (four 4-byte reads and one
+// 16-byte write per lane), before the barrier that hands the tile to the compute.
+// 16-byte copies move four times as much per instruction as 4-byte ones, which is
+// what bounds the staging rate.
 struct SchedLds {
     unsigned* scalars;    // 32 words
     float* out;           // [waves][4][128] each wave's outputs of one tile (its two blocks)
@@ -339,39 +396,95 @@ struct SchedLds {
     uint32_t ovf;         // LDS byte address of the overflow area
     int N;
     __device__ __forceinline__ SchedLds(float* lds, int n)
-        : scalars(reinterpret_cast<unsigned*>(lds + 8 * n)), out(lds + 8 * n + SCHED_SCALARS / 4),
-          base((uint32_t)(uintptr_t)lds), ovf((uint32_t)(uintptr_t)lds + 32u * n + SCHED_SCALARS + SCHED_OUT), N(n) {}
-    // The copies of a tile's 4 rows into buffer `buf` come in chunks of 16 ids x 4 rows
-    // (256 bytes; lane l brings row l % 4 of id 16c + l / 4, so the chunk lands as
-    // [id][row]); wave w issues chunks w, w + waves, ...  `row` is the lane's row
-    // (tile row l % 4).  Scalar base (src + 16c floats) + 32-bit lane offset; the
-    // caller guarantees rows * N * 4 < 2^32.
-    __device__ __forceinline__ int chunks(int wave, int waves) const {
-        const int total = N >> 4;
+        : scalars(reinterpret_cast<unsigned*>(lds + sched_tile_bytes(n) / 4)),
+          out(lds + sched_tile_bytes(n) / 4 + SCHED_SCALARS / 4), base((uint32_t)(uintptr_t)lds),
+          ovf((uint32_t)(uintptr_t)lds + (uint32_t)sched_tile_bytes(n) + SCHED_SCALARS + SCHED_OUT), N(n) {}
+    // blocks of 64 ids; the last one may be partial (N % 64 ids)
+    __device__ __forceinline__ int blocks() const { return (N + 63) >> 6; }
+    // blocks a wave copies (and transposes): wave, wave + waves, ...
+    __device__ __forceinline__ int blocks_of(int wave, int waves) const {
+        const int total = blocks();
         return wave < total ? (total - wave + waves - 1) / waves : 0;
     }
-    __device__ __forceinline__ void stage_chunk(const float* src, uint32_t voff, int wave, int waves, int i,
-                                                int buf) const {
-        const int c = wave + i * waves;
-        const uint64_t gb = (uint64_t)(uintptr_t)(src + 16 * (size_t)c);
+    // the lane's byte offset within a block copy: row `row` (the tile row l / 16),
+    // ids 4 (l % 16) .. +3
+    __device__ __forceinline__ uint32_t lane_off(int row, int lane) const {
+        return 4u * ((uint32_t)row * (uint32_t)N + 4u * (uint32_t)(lane & 15));
+    }
+    // A wave's copies of one tile as a cursor: blocks m = wave + i * waves, i = 0 ..
+    // full-1, then the partial last block (if this wave owns it) with its lanes past
+    // N switched off.  Scalar source address (id 64m of row 0) and LDS destination
+    // advance by one stride per copy.  The caller guarantees rows * N * 4 < 2^32.
+    template <int WAVES>
+    struct Cursor {
+        uint64_t src;     // global byte address of id 64m of row 0 (the lane's row is in voff)
+        uint32_t dst;     // LDS byte address of block m in the target buffer
+        uint32_t voff;
+        int full;         // full blocks left
+        int partial;      // 1: the partial last block after them
+        bool lane_in;     // the lane's ids of the partial block are < N
+        __device__ __forceinline__ void copy() const {
+            uint32_t saved;
+            __asm__ volatile(
+                "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %1, %3\n\ts_mov_b32 m0, %0"
+                : "=&s"(saved) : "v"(voff), "s"(dst), "s"(src) : "memory");
+        }
+        __device__ __forceinline__ void issue() {
+            if (full > 0) {
+                copy();
+                src += 256u * WAVES;
+                dst += 2048u * WAVES;
+                --full;
+            }
+        }
+        __device__ __forceinline__ void finish() {
+            while (full > 0) issue();
+            if (partial) {
+                if (lane_in) copy();
+                partial = 0;
+            }
+        }
+    };
+    template <int WAVES>
+    __device__ __forceinline__ Cursor<WAVES> cursor(const float* src, int row, int lane, int wave, int buf,
+                                                    bool on) const {
+        Cursor<WAVES> k;
+        const uint64_t gb = (uint64_t)(uintptr_t)(src + 64 * wave);
         // (readfirstlane returns int: widen through uint32_t, never by sign extension)
         const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)gb);
         const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(gb >> 32));
-        const uint64_t sb = ((uint64_t)hi << 32) | (uint64_t)lo;
-        const uint32_t dst = __builtin_amdgcn_readfirstlane(base + 512u * (uint32_t)c + 256u * (uint32_t)buf);
-        uint32_t saved;
-        __asm__ volatile(
-            "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %3\n\tglobal_load_lds_dword %1, %2\n\ts_mov_b32 m0, %0"
-            : "=&s"(saved) : "v"(voff), "s"(sb), "s"(dst) : "memory");
+        k.src = ((uint64_t)hi << 32) | (uint64_t)lo;
+        k.dst = __builtin_amdgcn_readfirstlane(base + 2048u * (uint32_t)wave + 1024u * (uint32_t)buf);
+        k.voff = lane_off(row, lane);
+        const int n = on ? blocks_of(wave, WAVES) : 0;
+        const bool has_partial = (N & 63) && n > 0 && wave + (n - 1) * WAVES == blocks() - 1;
+        k.full = has_partial ? n - 1 : n;
+        k.partial = has_partial ? 1 : 0;
+        k.lane_in = 4 * (lane & 15) < (N & 63);
+        return k;
     }
-    // the lane's offset for row `row`: row * N + (lane >> 2) floats, in bytes
-    __device__ __forceinline__ uint32_t lane_off(int row, int lane) const {
-        return 4u * ((uint32_t)row * (uint32_t)N + (uint32_t)(lane >> 2));
-    }
-    __device__ __forceinline__ void stage(const float* src, int row, int wave, int lane, int waves, int buf) const {
-        const int nc = chunks(wave, waves);
-        const uint32_t voff = lane_off(row, lane);
-        for (int i = 0; i < nc; ++i) stage_chunk(src, voff, wave, waves, i, buf);
+    // The wave's landed blocks of buffer `buf`, [row][id] -> [id][row] in place (the
+    // caller has waited for its copies): lane l gathers the 4 rows of id 64m + l and
+    // writes them back as one 16-byte slot.  NB blocks at a time: all their reads
+    // are issued before any write, and LDS serves a wave's instructions in order.
+    // (Slots of ids >= N in a partial block get junk, which nothing reads.)
+    template <int WAVES, int NB>
+    __device__ __forceinline__ void transpose(int wave, int lane, int buf) const {
+        const int n = blocks_of(wave, WAVES);
+        const uint32_t a0 = base + 2048u * (uint32_t)wave + 1024u * (uint32_t)buf + 4u * (uint32_t)lane;
+        for (int i0 = 0; i0 < n; i0 += NB) {
+            float x[NB][4];
+#pragma unroll
+            for (int u = 0; u < NB; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    x[u][r] = i0 + u < n ? lds_read4(a0 + 2048u * WAVES * (uint32_t)(i0 + u) + 256u * r) : 0.f;
+#pragma unroll
+            for (int u = 0; u < NB; ++u)
+                if (i0 + u < n)
+                    lds_write16(a0 - 4u * (uint32_t)lane + 2048u * WAVES * (uint32_t)(i0 + u) + 16u * (uint32_t)lane,
+                                make_float4(x[u][0], x[u][1], x[u][2], x[u][3]));
+        }
     }
 };
 
@@ -406,32 +519,6 @@ __device__ __forceinline__ int part_progress(int v, unsigned tag) {
     return ((unsigned)v & 0xfff00000u) == tag ? (int)((unsigned)v & 0xfffffu) : -1;
 }
 
-// 16-byte LDS read at an absolute LDS byte address (the offsets already include
-// the workgroup's LDS base), so the address register is used as is.
-__device__ __forceinline__ float4 lds_read16(uint32_t addr) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    typedef float v4f __attribute__((ext_vector_type(4)));
-    __builtin_assume((addr & 15u) == 0u);
-    const v4f r = *reinterpret_cast<const v4f __attribute__((address_space(3)))*>(addr);
-    return make_float4(r.x, r.y, r.z, r.w);
-#else
-    (void)addr;   // host pass of a device-only function
-    return make_float4(0.f, 0.f, 0.f, 0.f);
-#endif
-}
-
-// 8-byte LDS read at an absolute LDS byte address.
-__device__ __forceinline__ uint2 lds_read8(uint32_t addr) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    typedef unsigned v2u __attribute__((ext_vector_type(2)));
-    __builtin_assume((addr & 7u) == 0u);
-    const v2u r = *reinterpret_cast<const v2u __attribute__((address_space(3)))*>(addr);
-    return make_uint2(r.x, r.y);
-#else
-    (void)addr;
-    return make_uint2(0u, 0u);
-#endif
-}
 
 // One lane's resident neuron: schedule offsets and weights of one 64-neuron block.
 // Steps past DMAX (rare long blocks) are kept in LDS as (offset, weight) pairs
@@ -488,6 +575,16 @@ struct SchedNeuron {
     }
 };
 
+// An empty asm that takes 16 values as inputs and outputs: the compiler must have
+// all of them (one wait for the last) before the asm and cannot move their uses
+// above it.
+__device__ __forceinline__ void consume16(float4 (&v)[4]) {
+    __asm__ volatile(""
+                     : "+v"(v[0].x), "+v"(v[0].y), "+v"(v[0].z), "+v"(v[0].w), "+v"(v[1].x), "+v"(v[1].y),
+                       "+v"(v[1].z), "+v"(v[1].w), "+v"(v[2].x), "+v"(v[2].y), "+v"(v[2].z), "+v"(v[2].w),
+                       "+v"(v[3].x), "+v"(v[3].y), "+v"(v[3].z), "+v"(v[3].w));
+}
+
 // hook(g) runs at the start of group g (for every g with 4g < D): the caller's way
 // of spreading memory instructions over the compute instead of issuing them in a
 // burst that fills the memory pipeline and blocks the waves at issue.
@@ -498,17 +595,24 @@ __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_bas
     // group g (ping-pong register sets).  Steps past D are padding (weight 0, a
     // conflict-free read), so reading one group ahead is always safe.
     static_assert(DMAX % 4 == 0, "groups of 4");
-    const int D = n.D;
+    // D is re-read through an empty asm each time, so the compiler compares it per
+    // group (two scalar instructions) instead of keeping a mask per group alive
+    int D = n.D;
+    __asm__ volatile("" : "+s"(D));
     float4 v[2][4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[0][u] = lds_read16(n.off[u] + BUF * 256);
+    for (int u = 0; u < 4; ++u) v[0][u] = lds_read16(n.off[u] + BUF * 1024);
 #pragma unroll
     for (int g = 0; g < DMAX / 4; ++g) {
         if (4 * g < D) {
             hook(g);
             if (g + 1 < DMAX / 4) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) v[(g + 1) & 1][u] = lds_read16(n.off[4 * (g + 1) + u] + BUF * 256);
+                for (int u = 0; u < 4; ++u) v[(g + 1) & 1][u] = lds_read16(n.off[4 * (g + 1) + u] + BUF * 1024);
+                // one wait for the whole group (the 4 reads just issued stay in flight):
+                // the empty asm consumes the group's values, so the compiler waits for
+                // all four at once instead of before each step's FMAs
+                consume16(v[g & 1]);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -535,7 +639,7 @@ __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_bas
                     e[u] = lds_read8(n.ovf + (uint32_t)(min(st0 + u, D - 1) - DMAX) * 512u + 8u * (uint32_t)lane);
                 float4 c[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) c[u] = lds_read16(e[u].x + BUF * 256);
+                for (int u = 0; u < 4; ++u) c[u] = lds_read16(e[u].x + BUF * 1024);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const float w = st0 + u < D ? __uint_as_float(e[u].y) : 0.f;
@@ -549,7 +653,7 @@ __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_bas
             for (int st = DMAX; st < D; ++st) {
                 const uint32_t e = a.ent[(size_t)st * (a.nblk * 64) + n.slot];
                 const float w = n.weight_of(a, e, st);
-                const float4 c = lds_read16(lds_base + ((e >> 5) & 0x03ffffffu) + BUF * 256);
+                const float4 c = lds_read16(lds_base + ((e >> 5) & 0x03ffffffu) + BUF * 1024);
                 acc[0] = fmaf(w, c.x, acc[0]);
                 acc[1] = fmaf(w, c.y, acc[1]);
                 acc[2] = fmaf(w, c.z, acc[2]);
@@ -617,6 +721,11 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
     };
     // rows of a tile whose ids are in ring slot `slot` (valid after the barrier that follows the copy)
     auto in_row = [&](int tile, int slot) -> int { return a.list_in ? s_pin[4 * slot + (lane & 3)] : a.row_base + pos_of(tile); };
+    // the input row of tile row t (the block copies' lanes take row lane / 16)
+    auto in_row_t = [&](int tile, int slot, int t) -> int {
+        const int pos = tile * T + t;
+        return a.list_in ? s_pin[4 * slot + t] : a.row_base + (pos < R ? pos : tile * T);
+    };
     auto out_row = [&](int tile, int slot) -> int {
         return (LINEAR && a.rows_out) ? s_pout[4 * slot + (lane & 3)] : in_row(tile, slot);
     };
@@ -671,7 +780,11 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
     __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
     __syncthreads();
     int row_c = in_row(q, 0), orow_c = out_row(q, 0);   // rows of the tile being computed next
-    L.stage(a.yin, row_c, wave, lane, WAVES, 0);
+    int rowx_c = in_row_t(q, 0, lane >> 4);
+    {
+        auto c0 = L.cursor<WAVES>(a.yin, rowx_c, lane, wave, 0, true);
+        c0.finish();
+    }
     int tile_p = -1, row_p = 0, orow_p = 0;          // the previous tile (outputs not yet stored)
     // Each wave stages its own outputs (its two blocks: neurons wbase .. wbase+127,
     // 4 rows) in a private 2 KB of LDS and stores them with 16-byte stores after the
@@ -694,8 +807,12 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
                 const float4 v = *reinterpret_cast<const float4*>(wout + e);
                 *reinterpret_cast<float4*>(a.yout + o) = v;
                 if (a.ycopy) *reinterpret_cast<float4*>(a.ycopy + o) = v;
-                if (!LINEAR && a.yzero && !((mine >> t) & 1u))
-                    *reinterpret_cast<float4*>(a.yzero + o) = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (!LINEAR && a.yzero && !((mine >> t) & 1u)) {
+                    // (a zero made here, so the compiler keeps no zero vector alive across the loop)
+                    float z;
+                    __asm__ volatile("v_mov_b32 %0, 0" : "=v"(z));
+                    *reinterpret_cast<float4*>(a.yzero + o) = make_float4(z, z, z, z);
+                }
             }
         }
     };
@@ -704,6 +821,7 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
         const int buf = it & 1;
         const int slot = it % 3;                     // row-bit word of this tile
         __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
+        L.transpose<WAVES, 4>(wave, lane, buf);      // this wave's blocks of the tile, now landed
         if (prog_q && tid == 0) {
             __hip_atomic_store(prog_q + p, (int)(tag | (unsigned)it), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (it > SCHED_AHEAD) {
@@ -739,28 +857,23 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
         if (more) {
             // ring slot (it + 1) & 1 holds tile + S's ids (copied a tile ago, waited above)
             row_c = in_row(tile + S, buf ^ 1);
+            rowx_c = in_row_t(tile + S, buf ^ 1, lane >> 4);
             orow_c = out_row(tile + S, buf ^ 1);
         }
         if (tile + 2 * S < ntiles) prefetch(tile + 2 * S, buf);
         if (prog_q && wave == 0 && lane < G) lds_copy4_coherent(prog_q + lane, s_prog + lane);
-        // the next tile's copies, two per compute group
-        const int nc = more ? L.chunks(wave, WAVES) : 0;
-        const uint32_t voff = L.lane_off(row_c, lane);
-        int ci = 0;
-        auto issue2 = [&](int) {
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-                if (ci < nc) L.stage_chunk(a.yin, voff, wave, WAVES, ci++, buf ^ 1);
-        };
+        // the next tile's block copies, one per compute group
+        auto cur = L.cursor<WAVES>(a.yin, rowx_c, lane, wave, buf ^ 1, more);
+        auto issue = [&](int) { cur.issue(); };
         float acc0[T] = {0.f, 0.f, 0.f, 0.f}, acc1[T] = {0.f, 0.f, 0.f, 0.f};
         if (buf == 0) {
-            sched_steps<DMAX, 0>(a, L.base, lane, n0, acc0, issue2);
-            sched_steps<DMAX1, 0>(a, L.base, lane, n1, acc1, issue2);
+            sched_steps<DMAX, 0>(a, L.base, lane, n0, acc0, issue);
+            sched_steps<DMAX1, 0>(a, L.base, lane, n1, acc1, issue);
         } else {
-            sched_steps<DMAX, 1>(a, L.base, lane, n0, acc0, issue2);
-            sched_steps<DMAX1, 1>(a, L.base, lane, n1, acc1, issue2);
+            sched_steps<DMAX, 1>(a, L.base, lane, n0, acc0, issue);
+            sched_steps<DMAX1, 1>(a, L.base, lane, n1, acc1, issue);
         }
-        while (ci < nc) L.stage_chunk(a.yin, voff, wave, WAVES, ci++, buf ^ 1);
+        cur.finish();
         unsigned bits = 0u;
 #pragma unroll
         for (int t = 0; t < T; ++t) {
@@ -841,7 +954,7 @@ __global__ __launch_bounds__(NT) void k_chain_sched(ChainArgs c) {
         a.parts = c.parts;
         a.nblk = c.nblk;
         run_layer_sched<NT, DMAX>(a, lds, R);
-        if (!grid_barrier(c.bar, gen, c.err, reinterpret_cast<int*>(lds + 2 * SCHED_T * N) + 4)) return;
+        if (!grid_barrier(c.bar, gen, c.err, reinterpret_cast<int*>(lds + sched_tile_bytes(N) / 4) + 4)) return;
     }
 }
 
@@ -928,11 +1041,6 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
             }
         }
     }
-    // rows of a tile are consecutive (padding positions repeat the tile's first row)
-    auto row_of = [&](int tile) -> int {
-        const int pos = tile * T + (lane & 3);
-        return pos < R ? pos : tile * T;
-    };
     float yo[T], dv[T];            // Y_{l+1} and dY of the lane's neuron for the next tile
     auto fetch = [&](int tile) {
 #pragma unroll
@@ -947,14 +1055,21 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
             }
         }
     };
+    // rows of a tile are consecutive (padding positions repeat the tile's first row)
+    auto row_of_t = [&](int tile, int t) -> int {
+        const int pos = tile * T + t;
+        return pos < R ? pos : tile * T;
+    };
     if (q < ntiles) {
-        L.stage(a.y_in, row_of(q), wave, lane, WAVES, 0);
+        auto c0 = L.cursor<WAVES>(a.y_in, row_of_t(q, lane >> 4), lane, wave, 0, true);
+        c0.finish();
         fetch(q);
     }
     int it = 0;
     for (int tile = q; tile < ntiles; tile += S, ++it) {
         const int buf = it & 1;
         __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
+        L.transpose<WAVES, 1>(wave, lane, buf);       // this wave's blocks of the tile, now landed
         __syncthreads();                             // tile in buffer buf; the other buffer is free
         // G of this tile from the values fetched a tile ago (before any copy is issued,
         // so reading them waits for nothing new)
@@ -967,19 +1082,15 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
         }
         const bool more = tile + S < ntiles;
         if (more) fetch(tile + S);
-        // the next tile's copies, two per compute group
-        const int nc = more ? L.chunks(wave, WAVES) : 0;
-        const uint32_t voff = L.lane_off(row_of(tile + S), lane);
-        int ci = 0;
+        // the next tile's block copies, one per compute group
+        auto cur = L.cursor<WAVES>(a.y_in, row_of_t(tile + S, lane >> 4), lane, wave, buf ^ 1, more);
 #pragma unroll
         for (int g4 = 0; g4 < DMAX / 4; ++g4) {
             if (4 * g4 < D) {
-#pragma unroll
-                for (int u = 0; u < 2; ++u)
-                    if (ci < nc) L.stage_chunk(a.y_in, voff, wave, WAVES, ci++, buf ^ 1);
+                cur.issue();
                 float4 v[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) v[u] = buf == 0 ? lds_read16(off[4 * g4 + u]) : lds_read16(off[4 * g4 + u] + 256);
+                for (int u = 0; u < 4; ++u) v[u] = buf == 0 ? lds_read16(off[4 * g4 + u]) : lds_read16(off[4 * g4 + u] + 1024);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     float s = acc[4 * g4 + u];
@@ -991,13 +1102,13 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
                 }
             }
         }
-        while (ci < nc) L.stage_chunk(a.y_in, voff, wave, WAVES, ci++, buf ^ 1);
+        cur.finish();
         if (D > DMAX) {
             if (ovf != ~0u) {
                 for (int st = DMAX; st < D; ++st) {
                     const uint32_t pa = ovf + (uint32_t)(st - DMAX) * 512u + 8u * (uint32_t)lane;
                     const uint2 e2 = lds_read8(pa);
-                    const float4 c = lds_read16(e2.x + 256u * (uint32_t)buf);
+                    const float4 c = lds_read16(e2.x + 1024u * (uint32_t)buf);
                     float s = __uint_as_float(e2.y);
                     s = fmaf(g[0], c.x, s);
                     s = fmaf(g[1], c.y, s);
@@ -1010,7 +1121,7 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
                 for (int st = DMAX; st < D; ++st) {
                     const uint32_t e2 = a.ent[(size_t)st * (a.nblk * 64) + slot];
                     if (e2 & 0x80000000u) continue;
-                    const float4 c = lds_read16(L.base + ((e2 >> 5) & 0x03ffffffu) + 256u * (uint32_t)buf);
+                    const float4 c = lds_read16(L.base + ((e2 >> 5) & 0x03ffffffu) + 1024u * (uint32_t)buf);
                     float s = pw[e2 & 31u];
                     s = fmaf(g[0], c.x, s);
                     s = fmaf(g[1], c.y, s);

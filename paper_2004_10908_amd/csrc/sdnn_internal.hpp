@@ -79,10 +79,17 @@ constexpr int SCHED_PROG = 1024;   // ints of the parts' progress words ([stream
 constexpr int SCHED_PART = 1024;   // neurons per workgroup ("part") of the scheduled kernels
 constexpr int SCHED_OUT = SCHED_T * SCHED_PART * 4;   // bytes of the output staging tile
 
-// LDS of the scheduled forward kernel: compute tile and landing area (4 rows of N
-// floats each), the scalars, the output staging tile, the overflow area.
+// The two tile buffers of the scheduled kernels: 4 rows of N floats each, stored
+// [id][row] (16 bytes per id) in blocks of 64 ids, the blocks of the two buffers
+// interleaved (block m of buffer b at byte 2048 m + 1024 b).
+__host__ __device__ inline size_t sched_tile_bytes(int N) { return (size_t)2048 * (size_t)((N + 63) / 64); }
+// LDS byte offset of input id in buffer 0 (buffer 1: + 1024)
+__host__ __device__ inline uint32_t sched_slot_offset(uint32_t id) { return ((id >> 6) << 11) | ((id & 63u) << 4); }
+
+// LDS of the scheduled forward kernel: the tile buffers, the scalars, the output
+// staging tile, the overflow area.
 inline size_t sched_lds_bytes(int N) {
-    return (size_t)2 * SCHED_T * N * sizeof(float) + SCHED_SCALARS + SCHED_OUT + (size_t)SCHED_OVF * 512;
+    return sched_tile_bytes(N) + SCHED_SCALARS + SCHED_OUT + (size_t)SCHED_OVF * 512;
 }
 
 // Whole forward pass run by the persistent kernel (all layers, one launch).
