@@ -801,7 +801,10 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
             const int e = (k * 64 + lane) * 4;
             const int t = e >> 7;                    // rows 2k (lanes 0..31) and 2k + 1
             const int col = e & 127;
-            const int ro = __shfl(LINEAR ? orow_p : row_p, t);
+            // rows 2k and 2k + 1 are held by lanes 2k and 2k + 1 (lane t: tile row t)
+            const int rsrc = LINEAR ? orow_p : row_p;
+            const int ra = __builtin_amdgcn_readlane(rsrc, 2 * k), rb = __builtin_amdgcn_readlane(rsrc, 2 * k + 1);
+            const int ro = (lane >> 5) ? rb : ra;
             if (t < nv && wbase + col < N) {
                 const size_t o = (size_t)ro * N + wbase + col;
                 const float4 v = *reinterpret_cast<const float4*>(wout + e);
@@ -821,7 +824,7 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
         const int buf = it & 1;
         const int slot = it % 3;                     // row-bit word of this tile
         __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
-        L.transpose<WAVES, 4>(wave, lane, buf);      // this wave's blocks of the tile, now landed
+        L.transpose<WAVES, 8>(wave, lane, buf);      // this wave's blocks of the tile, now landed
         if (prog_q && tid == 0) {
             __hip_atomic_store(prog_q + p, (int)(tag | (unsigned)it), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (it > SCHED_AHEAD) {
@@ -885,9 +888,10 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
         }
         if (live || (!LINEAR && a.yzero)) {
             // row bits of this part: its waves meet in LDS (read after the next barrier)
+            unsigned wbits = 0u;                     // the wave's row bits, from one ballot per row
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o);
-            if (lane == 0 && bits) atomicOr(&s_bits[slot], bits);
+            for (int t = 0; t < T; ++t) wbits |= __ballot((bits >> t) & 1u) ? (1u << t) : 0u;
+            if (lane == 0 && wbits) atomicOr(&s_bits[slot], wbits);
         }
         tile_p = tile;
         row_p = row_now;
