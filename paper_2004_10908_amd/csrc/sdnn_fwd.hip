@@ -471,19 +471,29 @@ struct SchedLds {
     template <int WAVES, int NB>
     __device__ __forceinline__ void transpose(int wave, int lane, int buf) const {
         const int n = blocks_of(wave, WAVES);
-        const uint32_t a0 = base + 2048u * (uint32_t)wave + 1024u * (uint32_t)buf + 4u * (uint32_t)lane;
+        const uint32_t r0 = base + 2048u * (uint32_t)wave + 1024u * (uint32_t)buf + 4u * (uint32_t)lane;
+        const uint32_t w0 = r0 + 12u * (uint32_t)lane;   // the lane's 16-byte slot in the block
         for (int i0 = 0; i0 < n; i0 += NB) {
+            // one uniform test per block; the reads of a present block are straight-line
             float x[NB][4];
+            // (addresses as base + a constant below 64 KB, so each read and write
+            // takes its offset as an immediate)
+            constexpr uint32_t BS = 2048u * WAVES;           // bytes between a wave's blocks
+            constexpr int PER = (int)(65536u / BS) > 0 ? (int)(65536u / BS) : 1;   // blocks per base
+            const uint32_t rb = r0 + BS * (uint32_t)i0, wb = w0 + BS * (uint32_t)i0;
 #pragma unroll
             for (int u = 0; u < NB; ++u)
+                if (i0 + u < n) {
+                    const uint32_t rbu = rb + BS * (uint32_t)(u / PER * PER);
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    x[u][r] = i0 + u < n ? lds_read4(a0 + 2048u * WAVES * (uint32_t)(i0 + u) + 256u * r) : 0.f;
+                    for (int r = 0; r < 4; ++r) x[u][r] = lds_read4(rbu + BS * (uint32_t)(u % PER) + 256u * r);
+                }
 #pragma unroll
             for (int u = 0; u < NB; ++u)
-                if (i0 + u < n)
-                    lds_write16(a0 - 4u * (uint32_t)lane + 2048u * WAVES * (uint32_t)(i0 + u) + 16u * (uint32_t)lane,
-                                make_float4(x[u][0], x[u][1], x[u][2], x[u][3]));
+                if (i0 + u < n) {
+                    const uint32_t wbu = wb + BS * (uint32_t)(u / PER * PER);
+                    lds_write16(wbu + BS * (uint32_t)(u % PER), make_float4(x[u][0], x[u][1], x[u][2], x[u][3]));
+                }
         }
     }
 };
