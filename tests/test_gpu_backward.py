@@ -46,7 +46,9 @@ def layer_sync_bounds(idx, w, clamp, y_in, y_out, dy, groups=256):
 
 
 @pytest.mark.parametrize("N,rows,layer_kind,clamp", [(64, 13, "he", 1.5), (1024, 77, "he", 2.0),
-                                                     (4096, 64, "he", 32.0), (4096, 200, "uniform", 32.0)])
+                                                     (4096, 64, "he", 32.0), (4096, 200, "uniform", 32.0),
+                                                     # partial last 64-id block (N % 64 = 16, 32)
+                                                     (1040, 45, "he", 32.0), (96, 21, "uniform", 2.0)])
 def test_layer_backward_synchronized(P, N, rows, layer_kind, clamp):
     """One layer: the GPU's dW, db, dY from given fp32 Y_l, Y_{l+1}, dY_{l+1} are within the
     summation-error bound of the exact (fp64) result on the same inputs."""

@@ -26,7 +26,9 @@ def _net(P, idx, w, b, rows, **kw):
 
 @pytest.mark.parametrize("N,rows,weight,bias,clamp", [
     (32, 1, "he", 0.1, 32.0), (64, 7, "he", -0.05, 1.5), (96, 37, "uniform", -0.3, 32.0),
-    (1000, 129, "he", 0.0, 2.0), (4096, 19, "const", -0.35, 32.0)])
+    (1000, 129, "he", 0.0, 2.0), (4096, 19, "const", -0.35, 32.0),
+    # two parts and a last 64-id block of 16 ids (partial block copies and transposes)
+    (1040, 23, "he", -0.1, 32.0)])
 def test_layer_sync_small_nets(P, N, rows, weight, bias, clamp):
     cfg = gen.tiny_config(N, 4, rows, seed=N + rows, weight=weight, bias=bias, clamp=clamp, row_density=True)
     idx, w, b = upload(cfg)
