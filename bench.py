@@ -327,6 +327,50 @@ def bench_extras(args, torch, np, P, gen, dev, net_c2, y0_c2, idx2, w2, b2):
         del idx, w, b, y0, o
         torch.cuda.empty_cache()
 
+    # Graph-construction forms over batches (the paper's stream-count experiment):
+    # the explicitly built graph (batches in turn, and merged), the persistent
+    # launch, eager launches round-robin over K streams, and the same launches
+    # captured from K streams into one graph.  Workspace = the nets' scratch memory.
+    from paper_2004_10908_amd.streams import StreamForward
+    sres = {}
+    for name, cfg in (("C3", gen.CONFIGS["C3"]), ("S2_20", gen.CONFIGS["S2"].with_(n_batches=20, batch_lo=1500,
+                                                                                   batch_hi=4500))):
+        idx, w, b = device_net(torch, gen, cfg, dev)
+        y0 = device_inputs(torch, cfg, dev)
+        off = [int(v) for v in gen.make_batches(cfg)]
+        net = P.Net(idx, w, b, max_rows=cfg.rows)
+        o = {}
+        net.forward(y0, batch_off=off, out=o)
+        r = {"batches": len(off) - 1, "rows": cfg.rows, "N": cfg.n_neurons, "layers": cfg.n_layers}
+        for eng in ("graph", "graph_merged", "persistent"):
+            net.set_exec(eng)
+            r[eng] = {"ms": round(time_forward(torch, net, y0, o, 2, 1, batch_off=off), 3),
+                      "workspace_MB": round(net.ws_bytes / 2**20, 1)}
+        base = o["y"].clone()
+        y = torch.empty_like(y0)
+        for cap in (False, True):
+            for k in ((1, 2, 4) if not cap else (1, 2, 4, 8)):
+                sf = StreamForward(idx, w, b, off, k, capture=cap)
+                sf.run(y0, y)
+                torch.cuda.synchronize()
+                same = bool(torch.equal(y, base))
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(2):
+                    sf.run(y0, y)
+                e1.record()
+                torch.cuda.synchronize()
+                r[("captured" if cap else "eager") + f"_{k}"] = {"ms": round(e0.elapsed_time(e1) / 2, 3),
+                                                                  "workspace_MB": round(sf.workspace_bytes / 2**20, 1),
+                                                                  "equal_to_graph": same}
+                sf.close()
+        sres[name] = r
+        log("streams " + name, r)
+        net.close()
+        del idx, w, b, y0, o, base, y
+        torch.cuda.empty_cache()
+    ex["streams"] = sres
+
     # G5: forward + backward (bwd/fwd ratio) on 4096 rows, checkpoints every 16 layers
     cfg = gen.CONFIGS["G5"]
     idx, w, b = device_net(torch, gen, cfg, dev)
