@@ -674,9 +674,10 @@ __device__ __forceinline__ void sched_steps(const LayerArgs& a, uint32_t lds_bas
 }
 
 // The scheduled layer over R rows (tiles of 4 rows; see the comment above).
-// Per tile: wait for the tile's copies and meet at a barrier; store the previous
-// tile's outputs and advance the liveness pipeline; transpose the landed rows
-// into the compute tile; meet again; issue the copies of the next tile; compute.
+// Per tile: wait for this wave's block copies of the tile and turn its blocks
+// into [id][row]; (lockstep); meet at the barrier; advance the liveness pipeline
+// and store the previous tile's outputs; compute, issuing the next tile's block
+// copies into the other buffer one per compute group; stage the outputs.
 // No memory load is waited for inside the compute: the row ids of a tile are
 // fetched two tiles ahead, output stores are issued a tile late, and the row
 // liveness (LINEAR = false, with a work list or alive flags) runs as a pipeline
