@@ -242,3 +242,35 @@ def test_determinism_run_to_run(P):
     ya = a["y"].clone()
     b2, _ = run_forward(net, y0, mode="persistent")
     assert torch.equal(ya, b2["y"])
+
+
+def test_kernel_timing_api(P):
+    """sdnn_set_timing / sdnn_kernel_time: one event pair per persistent launch, the
+    sum restarts after each read, the kernel time fits inside the wall time of the
+    calls, and other engines record nothing."""
+    import time
+    cfg = gen.CONFIGS["S2"].with_(n_neurons=1024, n_layers=12, rows=2000, seed=31)
+    idx, w, b = upload(cfg)
+    y0 = torch.from_numpy(gen.make_inputs(cfg)).to(DEV)
+    net = _net(P, idx, w, b, cfg.rows)
+    o = {}
+    net.set_exec("persistent")
+    net.forward(y0, out=o)
+    net.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        net.forward(y0, out=o)
+    ms, n = net.kernel_time()             # waits for the recorded events
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    assert n == 3 and 0.0 < ms <= wall_ms
+    assert net.kernel_time() == (0.0, 0)  # a new sum
+    net.set_exec("graph")
+    net.forward(y0, out=o)
+    assert net.kernel_time() == (0.0, 0)  # only the persistent kernel is timed
+    net.set_timing(False)
+    net.set_exec("persistent")
+    net.forward(y0, out=o)
+    torch.cuda.synchronize()
+    assert net.kernel_time()[1] == 0
+    net.close()
