@@ -14,6 +14,8 @@ Prints ONE JSON line.  Besides the required fields it carries:
   cpu_baseline  the FP64 oracle timed on this host on a bounded row sample
   extras        sustained (S2), batched vs plain (C3), bwd/fwd ratio (G5),
                 engine comparison and a full-live layer, when --extras is on
+  streams       with --streams C3,S2_20,C4: the stream/graph forms of the batched
+                forward (explicit graph, eager and captured over 1-8 streams)
 """
 from __future__ import annotations
 
@@ -46,6 +48,8 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (the reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale) and exit")
+    ap.add_argument("--streams", default="", metavar="CONFIGS",
+                    help="also time the stream/graph forms on these configs (C3,S2_20,C4)")
     ap.add_argument("--tune", action="store_true", default=True)
     ap.add_argument("--no-tune", dest="tune", action="store_false")
     return ap.parse_args()
@@ -208,6 +212,10 @@ def main():
         except Exception as e:  # extras never hide the headline
             extras["error"] = repr(e)
             log("extras failed:", repr(e))
+    if args.streams:
+        net.close()
+        torch.cuda.empty_cache()
+        extras["streams"] = bench_streams(args, torch, P, gen, dev)
     net.close()
     del y0, idx, w, b, out
     torch.cuda.empty_cache()
@@ -327,14 +335,49 @@ def bench_extras(args, torch, np, P, gen, dev, net_c2, y0_c2, idx2, w2, b2):
         del idx, w, b, y0, o
         torch.cuda.empty_cache()
 
-    # Graph-construction forms over batches (the paper's stream-count experiment):
-    # the explicitly built graph (batches in turn, and merged), the persistent
-    # launch, eager launches round-robin over K streams, and the same launches
-    # captured from K streams into one graph.  Workspace = the nets' scratch memory.
+    # G5: forward + backward (bwd/fwd ratio) on 4096 rows, checkpoints every 16 layers
+    cfg = gen.CONFIGS["G5"]
+    idx, w, b = device_net(torch, gen, cfg, dev)
+    y0 = device_inputs(torch, cfg, dev)
+    net = P.Net(idx, w, b, max_rows=cfg.rows, ckpt_every=16, flags=P.sdnn.SDNN_TRAINABLE)
+    net.set_exec("graph")
+    o = net.forward(y0, ckpt=True)
+    dy = torch.randn_like(o["y"]) * 1e-4
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        net.forward(y0, ckpt=True, out=o)
+        net.backward(y0, o["ckpt"], o["nz_rows"], o["n_nz"], dy)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    reps = 3
+    fwd_ms = bwd_ms = 0.0
+    for _ in range(reps):
+        e[0].record(stream)
+        net.forward(y0, ckpt=True, out=o)
+        e[1].record(stream)
+        net.backward(y0, o["ckpt"], o["nz_rows"], o["n_nz"], dy)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        fwd_ms += e[0].elapsed_time(e[1]) / reps
+        bwd_ms += e[1].elapsed_time(e[2]) / reps
+    ex["G5"] = {"fwd_ms": round(fwd_ms, 3), "bwd_ms": round(bwd_ms, 3), "bwd_over_fwd": round(bwd_ms / fwd_ms, 3),
+                "n_nz": int(o["n_nz"].item()), "fwd_edges_per_s": cfg.rows * cfg.nnz / (fwd_ms / 1e3)}
+    log("G5", ex["G5"])
+    net.close()
+    return ex
+
+
+def bench_streams(args, torch, P, gen, dev):
+    """Graph-construction forms over batches (the paper's stream-count experiment):
+    the explicitly built graph (batches in turn, and merged), the persistent launch,
+    eager launches round-robin over K streams, and the same launches captured from K
+    streams into one graph.  Workspace = the nets' scratch memory."""
     from paper_2004_10908_amd.streams import StreamForward
+    named = {"C3": gen.CONFIGS["C3"], "C4": gen.CONFIGS["C4"],
+             "S2_20": gen.CONFIGS["S2"].with_(n_batches=20, batch_lo=1500, batch_hi=4500)}
     sres = {}
-    for name, cfg in (("C3", gen.CONFIGS["C3"]), ("S2_20", gen.CONFIGS["S2"].with_(n_batches=20, batch_lo=1500,
-                                                                                   batch_hi=4500))):
+    for name in args.streams.split(","):
+        cfg = named[name]
         idx, w, b = device_net(torch, gen, cfg, dev)
         y0 = device_inputs(torch, cfg, dev)
         off = [int(v) for v in gen.make_batches(cfg)]
@@ -369,38 +412,7 @@ def bench_extras(args, torch, np, P, gen, dev, net_c2, y0_c2, idx2, w2, b2):
         net.close()
         del idx, w, b, y0, o, base, y
         torch.cuda.empty_cache()
-    ex["streams"] = sres
-
-    # G5: forward + backward (bwd/fwd ratio) on 4096 rows, checkpoints every 16 layers
-    cfg = gen.CONFIGS["G5"]
-    idx, w, b = device_net(torch, gen, cfg, dev)
-    y0 = device_inputs(torch, cfg, dev)
-    net = P.Net(idx, w, b, max_rows=cfg.rows, ckpt_every=16, flags=P.sdnn.SDNN_TRAINABLE)
-    net.set_exec("graph")
-    o = net.forward(y0, ckpt=True)
-    dy = torch.randn_like(o["y"]) * 1e-4
-    stream = torch.cuda.current_stream()
-    for _ in range(2):
-        net.forward(y0, ckpt=True, out=o)
-        net.backward(y0, o["ckpt"], o["nz_rows"], o["n_nz"], dy)
-    torch.cuda.synchronize()
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    reps = 3
-    fwd_ms = bwd_ms = 0.0
-    for _ in range(reps):
-        e[0].record(stream)
-        net.forward(y0, ckpt=True, out=o)
-        e[1].record(stream)
-        net.backward(y0, o["ckpt"], o["nz_rows"], o["n_nz"], dy)
-        e[2].record(stream)
-        torch.cuda.synchronize()
-        fwd_ms += e[0].elapsed_time(e[1]) / reps
-        bwd_ms += e[1].elapsed_time(e[2]) / reps
-    ex["G5"] = {"fwd_ms": round(fwd_ms, 3), "bwd_ms": round(bwd_ms, 3), "bwd_over_fwd": round(bwd_ms / fwd_ms, 3),
-                "n_nz": int(o["n_nz"].item()), "fwd_edges_per_s": cfg.rows * cfg.nnz / (fwd_ms / 1e3)}
-    log("G5", ex["G5"])
-    net.close()
-    return ex
+    return sres
 
 
 def cpu_baseline(args, np, gen, cfg, idx_h, w_h, b_h, y0_h):
