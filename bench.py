@@ -16,6 +16,8 @@ Prints ONE JSON line.  Besides the required fields it carries:
                 engine comparison and a full-live layer, when --extras is on
   streams       with --streams C3,S2_20,C4: the stream/graph forms of the batched
                 forward (explicit graph, eager and captured over 1-8 streams)
+  streamed      with --streamed: parameters in pinned host memory streamed through
+                two device slots vs the same kernels over resident parameters
 """
 from __future__ import annotations
 
@@ -50,6 +52,8 @@ def parse():
                          "FETCH_SIZE / WRITE_SIZE counter scale) and exit")
     ap.add_argument("--streams", default="", metavar="CONFIGS",
                     help="also time the stream/graph forms on these configs (C3,S2_20,C4)")
+    ap.add_argument("--streamed", action="store_true", default=False,
+                    help="also time the forward with parameters streamed from host memory")
     ap.add_argument("--tune", action="store_true", default=True)
     ap.add_argument("--no-tune", dest="tune", action="store_false")
     return ap.parse_args()
@@ -216,6 +220,10 @@ def main():
         net.close()
         torch.cuda.empty_cache()
         extras["streams"] = bench_streams(args, torch, P, gen, dev)
+    if args.streamed:
+        net.close()
+        torch.cuda.empty_cache()
+        extras["streamed"] = bench_streamed(args, torch, P, gen, dev)
     net.close()
     del y0, idx, w, b, out
     torch.cuda.empty_cache()
@@ -413,6 +421,51 @@ def bench_streams(args, torch, P, gen, dev):
         del idx, w, b, y0, o, base, y
         torch.cuda.empty_cache()
     return sres
+
+
+def bench_streamed(args, torch, P, gen, dev):
+    """Parameters in pinned host memory streamed through two device slots, against the
+    same kernels over resident parameters (layer by layer over all rows)."""
+    from paper_2004_10908_amd.streamed import StreamedForward
+    cases = (("C2_4096", gen.CONFIGS["C2"].with_(rows=4096)),
+             ("C4_1000x64", gen.CONFIGS["C4"].with_(rows=1000, n_layers=64)))
+    res = {}
+    for name, cfg in cases:
+        idx, w, b = device_net(torch, gen, cfg, dev)
+        y0 = device_inputs(torch, cfg, dev)
+        net = P.Net(idx, w, b, max_rows=cfg.rows, flags=P.sdnn.SDNN_NO_SCHEDULE | P.sdnn.SDNN_NO_COMPACTION)
+        ya, yb = torch.empty_like(y0), torch.empty_like(y0)
+
+        def resident():
+            src = y0
+            for l in range(cfg.n_layers):
+                dst = yb if (cfg.n_layers - 1 - l) % 2 == 0 else ya
+                net.layer(l, src, dst)
+                src = dst
+
+        sf = StreamedForward(idx.cpu().pin_memory(), w.cpu().pin_memory(), b.cpu().pin_memory(), cfg.rows)
+        out = torch.empty_like(y0)
+        r = {"N": cfg.n_neurons, "layers": cfg.n_layers, "rows": cfg.rows,
+             "param_bytes_per_forward": int(idx.numel() * 8 + b.numel() * 4), "slot_bytes": sf.slot_bytes}
+        for key, fn in (("resident", resident), ("streamed", lambda: sf.run(y0, out))):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(2):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            r[key + "_ms"] = round(e0.elapsed_time(e1) / 2, 3)
+        r["equal"] = bool(torch.equal(out, yb))
+        r["copy_GBps_if_all_exposed"] = round(r["param_bytes_per_forward"] / (r["streamed_ms"] / 1e3) / 1e9, 1)
+        res[name] = r
+        log("streamed " + name, r)
+        sf.close()
+        net.close()
+        del idx, w, b, y0, ya, yb, out
+        torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(args, np, gen, cfg, idx_h, w_h, b_h, y0_h):

@@ -60,6 +60,10 @@ typedef enum {
 #define SDNN_NO_COMPACTION 0x2u  /* process every row in every layer (results are identical) */
 #define SDNN_DEBUG_CHECKS  0x4u  /* validate idx/w/bias on the device at create time (synchronizes) */
 #define SDNN_AUTOTUNE      0x8u  /* time the kernel variants at create time and keep the fastest */
+#define SDNN_NO_SCHEDULE   0x10u /* build no create-time slot schedules: the streamed-weight kernels
+                                    read idx and w on every call, so the borrowed parameters (ids
+                                    included) may change between calls, e.g. when layers are
+                                    streamed through device slots */
 
 /* sdnn_set_exec modes */
 #define SDNN_EXEC_AUTO         0 /* GRAPH for one batch, GRAPH_MERGED for several */

@@ -82,6 +82,7 @@ void step_major(std::vector<uint32_t>& e, int L, size_t npad) {
 }
 
 bool sched_possible(const sdnn_desc& d) {
+    if (d.flags & SDNN_NO_SCHEDULE) return false;
     const int nblk = (d.n_neurons + 63) / 64;
     const int G = (nblk + 15) / 16;
     // the tile copies address a row as a 32-bit byte offset from the activation base
@@ -155,7 +156,7 @@ sdnn_status check_desc(const sdnn_desc* d) {
     } else if (d->ckpt_every < 0) {
         return fail(SDNN_EINVAL, "ckpt_every must be >= 0");
     }
-    if (d->flags & ~(SDNN_TRAINABLE | SDNN_NO_COMPACTION | SDNN_DEBUG_CHECKS | SDNN_AUTOTUNE))
+    if (d->flags & ~(SDNN_TRAINABLE | SDNN_NO_COMPACTION | SDNN_DEBUG_CHECKS | SDNN_AUTOTUNE | SDNN_NO_SCHEDULE))
         return fail(SDNN_EINVAL, "unknown flag bits 0x%x", d->flags);
     return SDNN_OK;
 }

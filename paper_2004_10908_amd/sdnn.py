@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libsdnn.so")
 SDNN_OK, SDNN_EINVAL, SDNN_ENOMEM, SDNN_EHIP, SDNN_EUNSUPPORTED, SDNN_EDEVICE = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "SDNN_OK", -1: "SDNN_EINVAL", -2: "SDNN_ENOMEM", -3: "SDNN_EHIP", -4: "SDNN_EUNSUPPORTED",
                 -5: "SDNN_EDEVICE"}
-SDNN_TRAINABLE, SDNN_NO_COMPACTION, SDNN_DEBUG_CHECKS, SDNN_AUTOTUNE = 0x1, 0x2, 0x4, 0x8
+SDNN_TRAINABLE, SDNN_NO_COMPACTION, SDNN_DEBUG_CHECKS, SDNN_AUTOTUNE, SDNN_NO_SCHEDULE = 0x1, 0x2, 0x4, 0x8, 0x10
 SDNN_EXEC_AUTO, SDNN_EXEC_EAGER, SDNN_EXEC_GRAPH, SDNN_EXEC_PERSISTENT, SDNN_EXEC_GRAPH_MERGED = 0, 1, 2, 3, 4
 EXEC_NAMES = {"auto": 0, "eager": 1, "graph": 2, "persistent": 3, "graph_merged": 4}
 

@@ -71,3 +71,12 @@ def test_null_arguments_fail_before_any_launch(L):
     assert lib.sdnn_set_exec(None, 0) == L.sdnn.SDNN_EINVAL
     lib.sdnn_destroy(None)                         # NULL-safe
     assert lib.sdnn_mse(None, None, -1, None, None, None) == L.sdnn.SDNN_EINVAL
+
+
+def test_no_schedule_flag_shrinks_the_workspace():
+    """SDNN_NO_SCHEDULE drops the per-layer schedules from the workspace of a net the
+    scheduled kernels would otherwise serve."""
+    import paper_2004_10908_amd as L
+    with_s = L.sdnn_workspace_size(L.make_desc(4096, 8, 1000))
+    without = L.sdnn_workspace_size(L.make_desc(4096, 8, 1000, flags=L.sdnn.SDNN_NO_SCHEDULE))
+    assert 0 < without < with_s
