@@ -18,6 +18,8 @@ Prints ONE JSON line.  Besides the required fields it carries:
                 forward (explicit graph, eager and captured over 1-8 streams)
   streamed      with --streamed: parameters in pinned host memory streamed through
                 two device slots vs the same kernels over resident parameters
+  table         with --table C1,C2,...: per-config edges/s, algorithmic GB/s and
+                roofline fraction, plain vs batched, C5 backward / forward
 """
 from __future__ import annotations
 
@@ -54,6 +56,8 @@ def parse():
                     help="also time the stream/graph forms on these configs (C3,S2_20,C4)")
     ap.add_argument("--streamed", action="store_true", default=False,
                     help="also time the forward with parameters streamed from host memory")
+    ap.add_argument("--table", default="", metavar="CONFIGS",
+                    help="also run the per-config results table (e.g. C1,C2,C3,C4,C5,S2,S3)")
     ap.add_argument("--tune", action="store_true", default=True)
     ap.add_argument("--no-tune", dest="tune", action="store_false")
     return ap.parse_args()
@@ -224,6 +228,10 @@ def main():
         net.close()
         torch.cuda.empty_cache()
         extras["streamed"] = bench_streamed(args, torch, P, gen, dev)
+    if args.table:
+        net.close()
+        torch.cuda.empty_cache()
+        extras["table"] = bench_table(args, torch, P, gen, dev)
     net.close()
     del y0, idx, w, b, out
     torch.cuda.empty_cache()
@@ -464,6 +472,67 @@ def bench_streamed(args, torch, P, gen, dev):
         sf.close()
         net.close()
         del idx, w, b, y0, ya, yb, out
+        torch.cuda.empty_cache()
+    return res
+
+
+def bench_table(args, torch, P, gen, dev):
+    """The per-config results table: nominal and live edges/s, algorithmic bytes /
+    time and its fraction of the HBM peak, for the plain form (batches one after
+    another through the layer graph) and the batched form (the faster of the merged
+    graph and the persistent launch); the forward + backward ratio for C5."""
+    res = {}
+    for name in args.table.split(","):
+        cfg = gen.CONFIGS[name]
+        N, L = cfg.n_neurons, cfg.n_layers
+        idx, w, b = device_net(torch, gen, cfg, dev)
+        y0 = device_inputs(torch, cfg, dev)
+        trainable = cfg.ckpt_every > 0
+        net = P.Net(idx, w, b, max_rows=cfg.rows, ckpt_every=cfg.ckpt_every,
+                    flags=P.sdnn.SDNN_TRAINABLE if trainable else 0)
+        net.tune(min(cfg.rows, 8192))
+        off = [int(v) for v in gen.make_batches(cfg)] if cfg.n_batches > 1 else None
+        o = {}
+        net.forward(y0, batch_off=off, out=o, profile=True)
+        prof = o["layer_rows"].cpu().numpy()
+        alg, live = forward_bytes(prof, N, L), live_edges(prof, N, L)
+        steps = 1 if L * N > 480 * 16384 else 3
+        r = {"rows": cfg.rows, "N": N, "layers": L, "alive_head": [int(v) for v in prof[:4]],
+             "alive_last": int(prof[L]), "alg_bytes": alg}
+        forms = [("plain", "graph")] + ([("merged", "graph_merged"), ("persistent", "persistent")] if off else
+                                        [("persistent", "persistent")])
+        for form, eng in forms:
+            net.set_exec(eng)
+            ms = time_forward(torch, net, y0, o, steps, 1, batch_off=off)
+            r[form] = {"ms": round(ms, 3), "nominal_edges_per_s": cfg.rows * cfg.nnz / (ms / 1e3),
+                       "live_edges_per_s": live / (ms / 1e3), "alg_GBps": round(alg / ms / 1e6, 1),
+                       "frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        if off:
+            best = min(("merged", "persistent"), key=lambda k: r[k]["ms"])
+            r["batched_best"] = best
+            r["batched_over_plain"] = round(r["plain"]["ms"] / r[best]["ms"], 3)
+        if trainable:
+            net.set_exec("graph")
+            ob = net.forward(y0, ckpt=True)
+            dy = torch.randn_like(ob["y"]) * 1e-4
+            for _ in range(2):
+                net.forward(y0, ckpt=True, out=ob)
+                net.backward(y0, ob["ckpt"], ob["nz_rows"], ob["n_nz"], dy)
+            torch.cuda.synchronize()
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record()
+            net.forward(y0, ckpt=True, out=ob)
+            e[1].record()
+            net.backward(y0, ob["ckpt"], ob["nz_rows"], ob["n_nz"], dy)
+            e[2].record()
+            torch.cuda.synchronize()
+            r["fwd_ckpt_ms"] = round(e[0].elapsed_time(e[1]), 3)
+            r["bwd_ms"] = round(e[1].elapsed_time(e[2]), 3)
+            r["bwd_over_fwd"] = round(r["bwd_ms"] / r["fwd_ckpt_ms"], 3)
+        res[name] = r
+        log("table " + name, r)
+        net.close()
+        del idx, w, b, y0, o
         torch.cuda.empty_cache()
     return res
 

@@ -501,7 +501,7 @@ sdnn_status backward_layer_sched(const sdnn_net_s* n, int l, const float* y_in, 
     void* dargs[] = {&da};
     HIPCHK(hipLaunchKernel(bwd_dw_sched_fn(), dim3(SCHED_GRID), dim3(2 * SCHED_NT), dargs, sh, s));
     hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for((int64_t)N * K + N)), dim3(256), 0, s, (const float*)n->pdw,
-                       (const float*)n->pdb, (int32_t)S, (int32_t)N, dw_l, db_l);
+                       (const float*)n->pdb, (int32_t)S, (int32_t)N, dw_l, db_l, nrows, (int32_t)SCHED_T);
     if (dy_in) {
         LayerArgs a{};
         a.yin = n->gbuf2;
@@ -1002,7 +1002,7 @@ sdnn_status sdnn_backward(sdnn_net net, const float* y0, int64_t rows, const flo
                                    dim3(bwd_threads()), dargs, bsh, s));
             hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for((int64_t)NK + N)), dim3(256), 0, s,
                                (const float*)net->pdw, (const float*)net->pdb, (int32_t)P_GROUPS, (int32_t)N,
-                               dw + (size_t)l * NK, dbias + (size_t)l * N);
+                               dw + (size_t)l * NK, dbias + (size_t)l * N, (const int32_t*)nullptr, (int32_t)1);
             if (l > 0 || dy0) {
                 BwdDyArgs ya{};
                 ya.y_out = seg(l - l0 + 1);
@@ -1059,7 +1059,8 @@ sdnn_status sdnn_layer_backward(sdnn_net net, int32_t layer, const float* y_in, 
     HIPCHK(hipLaunchKernel(bwd_dw_fn(), dim3(P_GROUPS, (N + bwd_threads() - 1) / bwd_threads()), dim3(bwd_threads()),
                            dargs, bsh, s));
     hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for((int64_t)NK + N)), dim3(256), 0, s, (const float*)net->pdw,
-                       (const float*)net->pdb, (int32_t)P_GROUPS, (int32_t)N, dw, dbias);
+                       (const float*)net->pdb, (int32_t)P_GROUPS, (int32_t)N, dw, dbias, (const int32_t*)nullptr,
+                       (int32_t)1);
     if (dy_in && rows > 0) {
         BwdDyArgs ya{};
         ya.y_out = y_out;

@@ -145,7 +145,12 @@ const void* bwd_dw_fn() { return (const void*)&k_bwd_dw; }
 const void* bwd_dy_fn() { return (const void*)&k_bwd_dy; }
 
 // dW[j][k] = sum_{g < P} pdw[g][j][k] (in g order); db likewise.
-__global__ void k_reduce_partials(const float* pdw, const float* pdb, int32_t P, int32_t N, float* dw, float* db) {
+__global__ void k_reduce_partials(const float* pdw, const float* pdb, int32_t P, int32_t N, float* dw, float* db,
+                                  const int32_t* nrows, int32_t T) {
+    // with a row count: only the first ceil(R / T) partials were written (partial g
+    // holds tile stream g, and a stream past the tile count has no tile); R = 0 gives
+    // zero gradients
+    if (nrows) P = min(P, (*nrows + T - 1) / T);
     const int64_t nk = (int64_t)N * K;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nk + N; e += (int64_t)gridDim.x * blockDim.x) {
         if (e < nk) {

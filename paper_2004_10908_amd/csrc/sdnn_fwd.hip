@@ -1014,6 +1014,8 @@ __global__ __launch_bounds__(NT) void k_bwd_dw_sched(SchedDwArgs a) {
     const int q = (kk / G) * 8 + x;
     const int S = (int)gridDim.x / G;
     const int ntiles = (R + T - 1) / T;
+    // a stream with no tile writes no partials (the reduction stops before it)
+    if (q >= ntiles) return;                         // uniform over the workgroup
     const int blk = p * 16 + wave;
     const bool have = blk < a.nblk;
     const int slot = blk * 64 + lane;

@@ -189,7 +189,9 @@ const void* bwd_dw_sched_fn();
 const void* bwd_dy_sched_fn();
 const void* bwd_dw_fn();
 const void* bwd_dy_fn();
-__global__ void k_reduce_partials(const float* pdw, const float* pdb, int32_t P, int32_t N, float* dw, float* db);
+// sum the first P per-stream partials (with nrows: the first min(P, ceil(*nrows / T)))
+__global__ void k_reduce_partials(const float* pdw, const float* pdb, int32_t P, int32_t N, float* dw, float* db,
+                                  const int32_t* nrows, int32_t T);
 __global__ void k_gather_rows(const float* src, const int32_t* rows, const int32_t* n, int32_t N, float* dst);
 __global__ void k_tr_count(const int32_t* idx, int64_t nnz, int32_t* deg);
 __global__ void k_tr_scan(const int32_t* deg, int32_t N, int32_t* ptr);
