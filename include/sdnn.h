@@ -88,7 +88,10 @@ typedef struct {
     int32_t threads;         /* workgroup size */
     int32_t grid;            /* workgroups per layer launch (grid-stride over tiles) */
     int32_t variant;         /* 2 = scheduled resident-weight kernel, 0 = LDS-staged rows,
-                                1 = direct gather (rows too wide for LDS) */
+                                1 = direct gather (rows too wide for LDS),
+                                3 = wide layers: rows packed T per tile [N][T] in the workspace,
+                                    one T*4-byte gather per slot (forward-only nets whose
+                                    shape the scheduled kernel cannot take) */
     float tuned_us;          /* measured time per full-live layer of the tuning shape (0 if untuned) */
 } sdnn_plan;
 
@@ -118,6 +121,14 @@ sdnn_status sdnn_set_exec(sdnn_net net, int32_t mode);
 
 /* Read the current tile plan. */
 sdnn_status sdnn_get_plan(sdnn_net net, sdnn_plan *plan);
+
+/* Select the kernel variant given by plan->rows_per_tile, plan->threads and
+ * plan->variant (plan->grid and plan->tuned_us are ignored; the grid follows from
+ * the variant's occupancy).  SDNN_EINVAL if no variant has those three values,
+ * SDNN_EUNSUPPORTED if it does not fit this net (LDS, schedule, workspace).  Variants
+ * of one family (0, 1 and 3; or 2) give bitwise-equal results.  Not thread-safe
+ * against calls on the same net. */
+sdnn_status sdnn_set_plan(sdnn_net net, const sdnn_plan *plan);
 
 /*
  * Kernel timing (measurement support, not part of the method).  With enable != 0,
@@ -160,7 +171,8 @@ sdnn_status sdnn_forward(sdnn_net net, const float *y0, int64_t rows, const int6
 
 /*
  * One layer over all `rows` rows, no compaction: y_out = min(c, max(0, y_in W_l + b_l)).
- * Used to check the forward layer by layer.  y_in/y_out dev fp32 [rows][N], must not overlap.
+ * Used to check the forward layer by layer.  y_in/y_out dev fp32 [rows][N], must not overlap;
+ * rows <= max_rows (the wide-layer kernels pack the rows into the workspace).
  */
 sdnn_status sdnn_layer(sdnn_net net, int32_t layer, const float *y_in, int64_t rows, float *y_out, void *stream);
 

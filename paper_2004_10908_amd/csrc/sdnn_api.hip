@@ -53,6 +53,8 @@ constexpr int NBAR = BAR_WORDS;
 constexpr size_t LDS_BUDGET = 160 * 1024;       // dynamic LDS a workgroup may use (gfx950 maximum)
 constexpr int MSE_BLOCKS = 256;
 constexpr int SCHED_GRID = 256;                 // workgroups of the scheduled kernels (8 XCDs x 32)
+constexpr int WIDE_DEFAULT_T = 32;               // default tile of the wide-layer kernels (before tuning)
+constexpr int WIDE_DEFAULT_NT = 512;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
@@ -61,6 +63,8 @@ struct Layout {
     size_t ent = 0, lane_neuron = 0, wave_steps = 0, tile_bits = 0, prog = 0;
     size_t ent_t = 0, ent_w = 0, lane_input = 0, steps_t = 0, gbuf2 = 0;
     bool sched = false;
+    bool wide = false;
+    size_t packed = 0, wide_words = 0;
     size_t tr_ptr = 0, tr_e = 0, seg = 0, gbuf0 = 0, gbuf1 = 0, pdw = 0, pdb = 0;
     size_t total = 0;
 };
@@ -81,8 +85,7 @@ void step_major(std::vector<uint32_t>& e, int L, size_t npad) {
     e.swap(t);
 }
 
-bool sched_possible(const sdnn_desc& d) {
-    if (d.flags & SDNN_NO_SCHEDULE) return false;
+bool sched_shape(const sdnn_desc& d) {
     const int nblk = (d.n_neurons + 63) / 64;
     const int G = (nblk + 15) / 16;
     // the tile copies address a row as a 32-bit byte offset from the activation base
@@ -90,6 +93,11 @@ bool sched_possible(const sdnn_desc& d) {
     return d.n_neurons % 16 == 0 && sched_lds_bytes(d.n_neurons) <= LDS_BUDGET && (G == 1 || G == 2 || G == 4) &&
            offs32;
 }
+bool sched_possible(const sdnn_desc& d) { return !(d.flags & SDNN_NO_SCHEDULE) && sched_shape(d); }
+
+// The wide-layer kernels (packed row tiles) serve forward-only nets whose shape the
+// scheduled kernel cannot take; their packed buffer holds every row once more.
+bool wide_possible(const sdnn_desc& d) { return !trainable(d) && !sched_shape(d); }
 
 Layout make_layout(const sdnn_desc& d) {
     Layout y;
@@ -113,6 +121,12 @@ Layout make_layout(const sdnn_desc& d) {
         y.wave_steps = take(L * nblk * 4);
         y.tile_bits = take(((R + SCHED_T - 1) / SCHED_T) * 4);
         y.prog = take(SCHED_PROG * 4);
+    }
+    y.wide = wide_possible(d);
+    if (y.wide) {
+        const size_t rt = (R + WIDE_TMAX - 1) / WIDE_TMAX * WIDE_TMAX;
+        y.packed = take(rt * N * 4);
+        y.wide_words = take(2 * ((R + WIDE_TMIN - 1) / WIDE_TMIN) * 4);
     }
     y.bar = take(NBAR * 4);
     y.err = take(64);
@@ -211,6 +225,9 @@ struct sdnn_net_s {
     float *seg = nullptr, *gbuf0 = nullptr, *gbuf1 = nullptr, *pdw = nullptr, *pdb = nullptr;
     bool compaction = true;
     bool sched = false;                 // scheduled kernel available (schedule built)
+    bool wide = false;                  // wide-layer kernels available (packed buffer present)
+    float* packed = nullptr;
+    int32_t* wide_words = nullptr;
     uint32_t* ent = nullptr;
     int32_t *lane_neuron = nullptr, *wave_steps = nullptr, *tile_bits = nullptr, *prog = nullptr;
     int parts = 1, nblk = 0;
@@ -238,6 +255,7 @@ namespace {
 const FwdVariant& var(const sdnn_net_s* n) { return fwd_variant(n->variant); }
 
 bool variant_fits(const sdnn_net_s* n, const FwdVariant& v) {
+    if (v.staged == 3) return n->wide;
     if (v.staged == 2) return n->sched;
     if (!v.staged) return true;
     return (size_t)v.T * n->d.n_neurons * 4 <= LDS_BUDGET;
@@ -245,6 +263,8 @@ bool variant_fits(const sdnn_net_s* n, const FwdVariant& v) {
 
 // Schedule fields of layer l (the scheduled kernel reads them; others ignore them).
 void fill_sched(const sdnn_net_s* n, LayerArgs& a, int l) {
+    a.packed = n->packed;
+    a.wide_words = n->wide_words;
     if (!n->sched) return;
     const size_t npad = (size_t)n->nblk * 64;
     a.ent = n->ent + (size_t)l * npad * SCHED_DSTORE;
@@ -259,7 +279,7 @@ void fill_sched(const sdnn_net_s* n, LayerArgs& a, int l) {
 // Workgroups of a layer launch: grid-stride kernels shrink to the tile count; the
 // scheduled kernel keeps its full (XCD x part) grid and idle workgroups exit.
 int launch_grid(const sdnn_net_s* n, const FwdVariant& v, int64_t rows) {
-    if (v.staged == 2) return n->grid;
+    if (v.staged >= 2) return n->grid;
     return (int)std::max<int64_t>(1, std::min<int64_t>(n->grid, (rows + v.T - 1) / v.T));
 }
 
@@ -299,12 +319,36 @@ int default_variant(const sdnn_net_s* n) {
         if (v.NT != want_nt) continue;
         if (v.T > bestT) { bestT = v.T; best = i; }
     }
+    // a row tile of 2 or more rows in LDS beats the packed tiles (16384 neurons: 15.6
+    // against 24.4 ms per 60000-row layer); with no LDS tile the packed tiles win by
+    // about 15x over 4-byte gathers straight from the rows (65536 neurons)
+    if (n->wide && best < 0)
+        for (int i = 0; i < fwd_variant_count(); ++i) {
+            const FwdVariant& v = fwd_variant(i);
+            if (v.staged == 3 && v.T == WIDE_DEFAULT_T && v.NT == WIDE_DEFAULT_NT) return i;
+        }
     if (best >= 0) return best;
     for (int i = 0; i < fwd_variant_count(); ++i) {
         const FwdVariant& v = fwd_variant(i);
         if (!v.staged && v.T == 1 && v.NT == 1024) return i;
     }
     return 0;
+}
+
+// Workgroups of the wide kernels' pack pass over up to `rows` rows.
+int pack_grid(const sdnn_net_s* n, const FwdVariant& v, int64_t rows) {
+    const int64_t tasks = (rows + v.T - 1) / v.T * ((n->d.n_neurons + 4 * WIDE_PACK_NT - 1) / (4 * WIDE_PACK_NT));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(tasks, (int64_t)n->num_cu * 8));
+}
+
+// One layer launch of variant v (the wide variants: the pack pass, then the layer).
+hipError_t launch_layer(const sdnn_net_s* n, const FwdVariant& v, int grid, LayerArgs& a, int64_t rows, hipStream_t s) {
+    void* args[] = {&a};
+    if (v.pack_fn) {
+        const hipError_t e = hipLaunchKernel(v.pack_fn, dim3(pack_grid(n, v, rows)), dim3(WIDE_PACK_NT), args, 0, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipLaunchKernel(v.layer_fn, dim3(grid), dim3(v.NT), args, fwd_lds_bytes(v, n->d.n_neurons), s);
 }
 
 sdnn_status issue(const Plan& plan, hipStream_t s, sdnn_net_s* n = nullptr) {
@@ -407,6 +451,7 @@ Plan plan_chain(const sdnn_net_s* n, const float* y0, int64_t rows, const int64_
                        (int32_t)(n->compaction ? 1 : 0), (unsigned*)nullptr, (int32_t)0));
         for (int l = 0; l < L; ++l) {
             LayerArgs a = layer_args_chain(n, l, y0, y_out, ckpt, rows, r0, nbr, cr);
+            if (v.pack_fn) p.push_back(mk(v.pack_fn, dim3(pack_grid(n, v, nbr)), dim3(WIDE_PACK_NT), 0, a));
             p.push_back(mk(v.layer_fn, dim3(launch_grid(n, v, nbr)), dim3(v.NT), sh, a));
         }
         ++region;
@@ -460,6 +505,8 @@ Plan plan_persistent(const sdnn_net_s* n, const float* y0, int64_t rows, float* 
         c.parts = n->parts;
         c.nblk = n->nblk;
     }
+    c.packed = n->packed;
+    c.wide_words = n->wide_words;
     auto ch = mk(v.chain_fn, dim3(n->chain_grid), dim3(v.NT), sh, c);
     ch->cooperative = true;
     ch->timed = true;
@@ -593,6 +640,11 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
         n->pdw = (float*)(n->ws + lay.pdw);
         n->pdb = (float*)(n->ws + lay.pdb);
     }
+    if (lay.wide) {
+        n->wide = true;
+        n->packed = (float*)(n->ws + lay.packed);
+        n->wide_words = (int32_t*)(n->ws + lay.wide_words);
+    }
     HIPCHK(hipGetDevice(&n->device));
     HIPCHK(hipDeviceGetAttribute(&n->num_cu, hipDeviceAttributeMultiprocessorCount, n->device));
 
@@ -602,6 +654,10 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, n->err, (int64_t)16, 0);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, n->flag, (int64_t)16, 0);
     hipLaunchKernelGGL(k_fill_i32, dim3(2), dim3(256), 0, s, (int32_t*)n->bar, (int64_t)NBAR, 0);
+    if (n->wide) {
+        const int64_t nw = 2 * ((std::max<int64_t>(desc->max_rows, 1) + WIDE_TMIN - 1) / WIDE_TMIN);
+        hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nw)), dim3(256), 0, s, n->wide_words, nw, 0);
+    }
     HIPCHK(hipGetLastError());
     if (desc->flags & SDNN_DEBUG_CHECKS) {
         hipLaunchKernelGGL(k_check_params, dim3(blocks_for((int64_t)N * L)), dim3(256), 0, s, idx, w, bias, N, L,
@@ -768,9 +824,29 @@ sdnn_status sdnn_get_plan(sdnn_net net, sdnn_plan* plan) {
     plan->rows_per_tile = v.T;
     plan->threads = v.NT;
     plan->grid = net->grid;
-    plan->variant = v.staged == 2 ? 2 : (v.staged ? 0 : 1);
+    plan->variant = v.staged >= 2 ? v.staged : (v.staged ? 0 : 1);
     plan->tuned_us = net->tuned_us;
     return SDNN_OK;
+}
+
+sdnn_status sdnn_set_plan(sdnn_net net, const sdnn_plan* plan) {
+    if (!net || !plan) return fail(SDNN_EINVAL, "NULL argument");
+    for (int vi = 0; vi < fwd_variant_count(); ++vi) {
+        const FwdVariant& v = fwd_variant(vi);
+        const int code = v.staged >= 2 ? v.staged : (v.staged ? 0 : 1);
+        if (v.T != plan->rows_per_tile || v.NT != plan->threads || code != plan->variant) continue;
+        if (!variant_fits(net, v))
+            return fail(SDNN_EUNSUPPORTED, "variant %d (T=%d, NT=%d) does not fit this net", code, v.T, v.NT);
+        int g = 0, cg = 0;
+        TRY(prepare_variant(net, vi, &g, &cg));
+        net->variant = vi;
+        net->grid = g;
+        net->chain_grid = cg;
+        drop_graph(net);
+        return SDNN_OK;
+    }
+    return fail(SDNN_EINVAL, "no kernel variant with T=%d, NT=%d, variant=%d", plan->rows_per_tile, plan->threads,
+                plan->variant);
 }
 
 sdnn_status sdnn_tune(sdnn_net net, int64_t rows, void* stream) {
@@ -806,13 +882,11 @@ sdnn_status sdnn_tune(sdnn_net net, int64_t rows, void* stream) {
         a.N = N;
         a.clamp = net->d.clamp;
         fill_sched(net, a, 0);
-        const int gg = v.staged == 2 ? g : std::max(1, std::min<int>(g, (int)((rt + v.T - 1) / v.T)));
-        void* args[] = {&a};
-        const size_t sh = fwd_lds_bytes(v, N);
-        HIPCHK(hipLaunchKernel(v.layer_fn, dim3(gg), dim3(v.NT), args, sh, s));
+        const int gg = v.staged >= 2 ? g : std::max(1, std::min<int>(g, (int)((rt + v.T - 1) / v.T)));
+        HIPCHK(launch_layer(net, v, gg, a, rt, s));
         HIPCHK(hipEventRecord(e0, s));
         const int reps = 3;
-        for (int r = 0; r < reps; ++r) HIPCHK(hipLaunchKernel(v.layer_fn, dim3(gg), dim3(v.NT), args, sh, s));
+        for (int r = 0; r < reps; ++r) HIPCHK(launch_layer(net, v, gg, a, rt, s));
         HIPCHK(hipEventRecord(e1, s));
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -899,7 +973,8 @@ sdnn_status sdnn_layer(sdnn_net net, int32_t layer, const float* y_in, int64_t r
     if (!net) return fail(SDNN_EINVAL, "net is NULL");
     const sdnn_desc& d = net->d;
     if (layer < 0 || layer >= d.n_layers) return fail(SDNN_EINVAL, "layer %d out of range", layer);
-    if (rows < 0 || rows > INT32_MAX) return fail(SDNN_EINVAL, "rows out of range");
+    if (rows < 0 || rows > d.max_rows) return fail(SDNN_EINVAL, "rows = %lld outside [0, max_rows = %lld]",
+                                                  (long long)rows, (long long)d.max_rows);
     if (rows == 0) return SDNN_OK;
     if (!y_in || !y_out) return fail(SDNN_EINVAL, "y_in and y_out are required");
     const size_t bytes = (size_t)rows * d.n_neurons * 4;
@@ -918,9 +993,7 @@ sdnn_status sdnn_layer(sdnn_net net, int32_t layer, const float* y_in, int64_t r
     a.layer = layer;
     a.clamp = d.clamp;
     fill_sched(net, a, layer);
-    const int g = launch_grid(net, v, rows);
-    void* args[] = {&a};
-    HIPCHK(hipLaunchKernel(v.layer_fn, dim3(g), dim3(v.NT), args, fwd_lds_bytes(v, d.n_neurons), (hipStream_t)stream));
+    HIPCHK(launch_layer(net, v, launch_grid(net, v, rows), a, rows, (hipStream_t)stream));
     return SDNN_OK;
 }
 
@@ -954,7 +1027,6 @@ sdnn_status sdnn_backward(sdnn_net net, const float* y0, int64_t rows, const flo
     const int gather_grid = std::min<int64_t>(rows, 8192);
     hipLaunchKernelGGL(k_gather_rows, dim3(gather_grid), dim3(256), 0, s, dy_out, nz_rows, n_nz, N, D);
     const FwdVariant& v = var(net);
-    const size_t fsh = fwd_lds_bytes(v, N);
     const int fgrid = launch_grid(net, v, rows);
     const size_t bsh = (size_t)bwd_T() * N * 4;
     const int dy_grid = std::max(1, std::min<int>(net->num_cu * 2, (int)((rows + bwd_T() - 1) / bwd_T())));
@@ -974,8 +1046,7 @@ sdnn_status sdnn_backward(sdnn_net net, const float* y0, int64_t rows, const flo
             a.layer = l;
             a.clamp = d.clamp;
             fill_sched(net, a, l);
-            void* args[] = {&a};
-            HIPCHK(hipLaunchKernel(v.layer_fn, dim3(fgrid), dim3(v.NT), args, fsh, s));
+            HIPCHK(launch_layer(net, v, fgrid, a, rows, s));
         }
         for (int l = l1 - 1; l >= l0; --l) {
             const bool sch = net->sched_bwd && var(net).staged == 2;

@@ -274,41 +274,255 @@ __global__ __launch_bounds__(FIN_NT) void k_finalize(const int32_t* alive, int32
 // as a layer's work list is empty.  Layer l writes X_l, which is y_out when
 // (L-1-l) is even and the workspace buffer otherwise, so the last layer always
 // lands in y_out.
+__device__ __forceinline__ LayerArgs chain_layer_args(const ChainArgs& c, int l, int R) {
+    const int N = c.N, L = c.L;
+    const size_t NK = (size_t)N * K;
+    const bool out_is_y = ((L - 1 - l) & 1) == 0;
+    LayerArgs a{};
+    a.yin = l == 0 ? c.y0 : (out_is_y ? c.act : c.y_out);
+    a.yout = out_is_y ? c.y_out : c.act;
+    a.ycopy = (c.ckpt && (l + 1) % c.ckpt_every == 0 && l + 1 < L)
+                  ? c.ckpt + (size_t)((l + 1) / c.ckpt_every - 1) * c.rows * N
+                  : nullptr;
+    a.yzero = (c.compaction && !out_is_y) ? c.y_out : nullptr;
+    a.idx = c.idx + l * NK;
+    a.w = c.w + l * NK;
+    a.b = c.b + (size_t)l * N;
+    a.list_in = (l == 0 || !c.compaction) ? nullptr : ((l & 1) ? c.list1 : c.list0);
+    a.list_out = c.compaction ? (((l + 1) & 1) ? c.list1 : c.list0) : nullptr;
+    a.cnt_in = nullptr;
+    a.cnt_out = &c.cnt[l + 1];
+    a.alive = c.alive;
+    a.row_base = 0;
+    a.nrows = R;
+    a.N = N;
+    a.layer = l;
+    a.clamp = c.clamp;
+    a.packed = c.packed;
+    a.wide_words = c.wide_words;
+    return a;
+}
+
 template <int T, int NT, bool STAGED>
 __global__ __launch_bounds__(NT) void k_chain(ChainArgs c) {
     extern __shared__ __align__(16) float lds[];
     __shared__ int s_ok;
     unsigned gen = 0u;
-    const int N = c.N, L = c.L;
-    const size_t NK = (size_t)N * K;
-    for (int l = 0; l < L; ++l) {
+    for (int l = 0; l < c.L; ++l) {
         const int R = (l == 0 || !c.compaction) ? c.rows : ld_acquire(&c.cnt[l]);
         if (R == 0) break;
-        const bool out_is_y = ((L - 1 - l) & 1) == 0;
-        LayerArgs a{};
-        a.yin = l == 0 ? c.y0 : (out_is_y ? c.act : c.y_out);
-        a.yout = out_is_y ? c.y_out : c.act;
-        a.ycopy = (c.ckpt && (l + 1) % c.ckpt_every == 0 && l + 1 < L)
-                      ? c.ckpt + (size_t)((l + 1) / c.ckpt_every - 1) * c.rows * N
-                      : nullptr;
-        a.yzero = (c.compaction && !out_is_y) ? c.y_out : nullptr;
-        a.idx = c.idx + l * NK;
-        a.w = c.w + l * NK;
-        a.b = c.b + (size_t)l * N;
-        a.list_in = (l == 0 || !c.compaction) ? nullptr : ((l & 1) ? c.list1 : c.list0);
-        a.list_out = c.compaction ? (((l + 1) & 1) ? c.list1 : c.list0) : nullptr;
-        a.cnt_in = nullptr;
-        a.cnt_out = &c.cnt[l + 1];
-        a.alive = c.alive;
-        a.row_base = 0;
-        a.nrows = R;
-        a.N = N;
-        a.layer = l;
-        a.clamp = c.clamp;
+        const LayerArgs a = chain_layer_args(c, l, R);
         run_layer<T, NT, STAGED>(a, lds, blockIdx.x, gridDim.x, R);
         if (!grid_barrier(c.bar, gen, c.err, &s_ok)) return;
     }
     // the nz list and the row profile are produced by a k_finalize launch after this kernel
+}
+
+// ---------------------------------------------------------------- wide-layer kernels
+// For layers too wide for a tile of several rows in LDS (the 65536- and
+// 16384-neuron nets), a layer is two passes:
+//  * pack: the rows of the work list, T at a time, are copied into a workspace
+//    buffer as tiles [tile][N][T], so the T values of one input id are contiguous;
+//  * compute: a gather of input id i is then T * 4 contiguous bytes serving T rows,
+//    instead of T scattered 4-byte loads; the T / 4 lanes of a neuron take 16 bytes
+//    (4 rows) each, so one load instruction reads whole slots.  Tile X goes to
+//    workgroup group X % 8 (group = blockIdx % 8, the XCD it runs on); the
+//    workgroups of a group split each of its tiles by chunks of 4 NT / T neurons
+//    (their 32 (id, weight) pairs read per tile), so a tile is fetched into that
+//    XCD's L2 once and gathered from there by all of them.  A group with at least
+//    twice as many workgroups as chunks runs several tile sub-streams.
+//    The last workgroup to finish a tile (a counter per tile) publishes its row
+//    liveness: list slots, alive flags, dead rows zeroed where asked.
+// The per-output arithmetic is run_layer's (slots in ascending order with fused
+// multiply-adds, then the bias), so outputs are bitwise equal to it.
+
+template <int T>
+__device__ __forceinline__ void wide_pack_body(const LayerArgs& a, int R, int wg, int nwg) {
+    __shared__ int32_t s_prow[T];
+    const int N = a.N;
+    const int nt = blockDim.x;
+    const int64_t ntiles = (R + T - 1) / T;
+    const int chunk = 4 * nt;                              // ids per task
+    const int64_t chunks = (N + chunk - 1) / chunk;
+    for (int64_t task = wg; task < ntiles * chunks; task += nwg) {
+        const int64_t tile = task / chunks;
+        const int c0 = (int)(task % chunks) * chunk;
+        __syncthreads();                                   // the previous task's row ids are read
+        if ((int)threadIdx.x < T) {
+            const int64_t p = tile * T + threadIdx.x;
+            s_prow[threadIdx.x] = p < R ? (a.list_in ? a.list_in[p] : a.row_base + (int32_t)p) : -1;
+        }
+        __syncthreads();
+        int32_t rr[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) rr[t] = s_prow[t];
+        float* dst = a.packed + (size_t)tile * N * T;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = c0 + q * nt + (int)threadIdx.x;
+            if (i < N) {
+                float v[T];
+#pragma unroll
+                for (int t = 0; t < T; ++t) v[t] = rr[t] >= 0 ? a.yin[(size_t)rr[t] * N + i] : 0.f;
+                float4* o = reinterpret_cast<float4*>(dst + (size_t)i * T);
+#pragma unroll
+                for (int h = 0; h < T / 4; ++h) o[h] = make_float4(v[4 * h], v[4 * h + 1], v[4 * h + 2], v[4 * h + 3]);
+            }
+        }
+    }
+}
+
+template <int T>
+__global__ __launch_bounds__(WIDE_PACK_NT) void k_wide_pack(LayerArgs a) {
+    const int R = a.cnt_in ? *a.cnt_in : a.nrows;
+    wide_pack_body<T>(a, R, blockIdx.x, gridDim.x);
+}
+
+// slot groups (4 slots each) whose gathers the compiler may keep in flight together
+constexpr int WIDE_UNROLL = 4;
+
+// The Q = T / 4 lanes of one neuron split the tile's rows, 4 each: lane quarter rq
+// reads bytes 16 rq .. 16 rq + 15 of the T * 4-byte slot, so one load instruction
+// fetches 64 / Q whole slots (contiguous segments) rather than 64 scattered pieces.
+template <int T, int NT>
+__device__ __forceinline__ void run_layer_wide(const LayerArgs& a, int wg, int nwg, int R) {
+    static_assert(T % 4 == 0 && T <= 32, "T rows must fit the 32 row bits of a tile word");
+    constexpr int Q = T / 4;                       // lanes per neuron
+    constexpr int NPC = NT / Q;                    // neurons per chunk
+    static_assert(64 % Q == 0 && NT % 64 == 0, "a neuron's lanes must sit in one wave");
+    __shared__ int32_t s_rows[T];
+    __shared__ unsigned s_bits;
+    __shared__ int s_last;
+    const int N = a.N;
+    const int tid = threadIdx.x;
+    const int rq = tid % Q;                        // rows 4 rq .. 4 rq + 3 of the tile
+    const int jl = tid / Q;                        // neuron within the chunk
+    const int ntiles = (R + T - 1) / T;
+    const int groups = nwg < 8 ? nwg : 8;
+    const int grp = wg & 7;                        // < groups: wg < nwg
+    const int gi = wg >> 3;                        // index within the group
+    const int gsize = (nwg - grp + 7) >> 3;        // workgroups of the group
+    const int nch = (N + NPC - 1) / NPC;           // neuron chunks
+    const int per = gsize < nch ? gsize : nch;     // workgroups sharing one tile
+    const int sub = gsize / per;                   // tile sub-streams of the group
+    const int s = gi / per, ci = gi % per;
+    if (s >= sub) return;                          // no share of any tile
+    for (int tile = grp + groups * s; tile < ntiles; tile += groups * sub) {
+        if (tid < T) {
+            const int p = tile * T + tid;
+            s_rows[tid] = p < R ? (a.list_in ? a.list_in[p] : a.row_base + p) : -1;
+        }
+        if (tid == 0) s_bits = 0u;
+        __syncthreads();
+        // rows past the list end sit at the tile's end
+        const int nvalid = R - tile * T < T ? R - tile * T : T;
+        const unsigned valid = nvalid >= 32 ? ~0u : ((1u << nvalid) - 1u);
+        const float4* tq = reinterpret_cast<const float4*>(a.packed + (size_t)tile * N * T) + rq;
+        unsigned bits = 0u;
+        for (int c = ci; c < nch; c += per) {
+            const int j = c * NPC + jl;
+            if (j < N) {
+                float acc[4] = {0.f, 0.f, 0.f, 0.f};
+                auto slot = [&](int i, float w) {
+                    const float4 v = tq[(size_t)i * Q];
+                    acc[0] = fmaf(w, v.x, acc[0]);
+                    acc[1] = fmaf(w, v.y, acc[1]);
+                    acc[2] = fmaf(w, v.z, acc[2]);
+                    acc[3] = fmaf(w, v.w, acc[3]);
+                };
+                const int4* ip = reinterpret_cast<const int4*>(a.idx + (size_t)j * K);
+                const float4* wp = reinterpret_cast<const float4*>(a.w + (size_t)j * K);
+#pragma unroll WIDE_UNROLL
+                for (int q = 0; q < K / 4; ++q) {
+                    const int4 iv = ip[q];
+                    const float4 wv = wp[q];
+                    slot(iv.x, wv.x);
+                    slot(iv.y, wv.y);
+                    slot(iv.z, wv.z);
+                    slot(iv.w, wv.w);
+                }
+                const float bj = a.b[j];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int row = 4 * rq + t;
+                    const float y = fminf(fmaxf(acc[t] + bj, 0.f), a.clamp);
+                    if (row < nvalid) {
+                        const size_t o = (size_t)s_rows[row] * N + j;
+                        a.yout[o] = y;
+                        if (a.ycopy) a.ycopy[o] = y;
+                    }
+                    bits |= (y != 0.f ? 1u : 0u) << row;
+                }
+            }
+        }
+        bits &= valid;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) bits |= __shfl_xor(bits, off);
+        if ((tid & 63) == 0 && bits) atomicOr(&s_bits, bits);
+        __syncthreads();
+        if (tid == 0) {
+            int32_t* wd = a.wide_words + 2 * (size_t)tile;
+            const unsigned mine = s_bits;
+            __threadfence();
+            if (mine) atomicOr(reinterpret_cast<unsigned*>(wd), mine);
+            __threadfence();
+            const int last = atomicAdd(wd + 1, 1) == per - 1;
+            if (last) {
+                __threadfence();
+                s_bits = (unsigned)__hip_atomic_load(wd, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                atomicExch(wd, 0);                 // every sharer has arrived: reset for the next layer
+                atomicExch(wd + 1, 0);
+            }
+            s_last = last;
+        }
+        __syncthreads();
+        if (s_last) {
+            const unsigned alive = s_bits;
+            if (tid == 0 && a.list_out) {
+                const int n = __popc(alive);
+                if (n) {
+                    int base = atomicAdd(a.cnt_out, n);
+#pragma unroll
+                    for (int t = 0; t < T; ++t)
+                        if ((alive >> t) & 1u) a.list_out[base++] = s_rows[t];
+                }
+            }
+            if (a.alive && tid < nvalid) a.alive[s_rows[tid]] = (int32_t)((alive >> tid) & 1u);
+            if (a.yzero) {
+                for (int t = 0; t < nvalid; ++t) {
+                    if (!((alive >> t) & 1u)) {
+                        float* z = a.yzero + (size_t)s_rows[t] * N;
+                        for (int i = tid; i < N; i += NT) z[i] = 0.f;
+                    }
+                }
+            }
+        }
+        __syncthreads();                           // s_rows, s_bits, s_last are reused
+    }
+}
+
+template <int T, int NT>
+__global__ __launch_bounds__(NT) void k_layer_wide(LayerArgs a) {
+    const int R = a.cnt_in ? *a.cnt_in : a.nrows;
+    run_layer_wide<T, NT>(a, blockIdx.x, gridDim.x, R);
+}
+
+// Persistent chain of the wide kernels: pack, grid barrier, compute, grid barrier.
+template <int T, int NT>
+__global__ __launch_bounds__(NT) void k_chain_wide(ChainArgs c) {
+    __shared__ int s_ok;
+    unsigned gen = 0u;
+    for (int l = 0; l < c.L; ++l) {
+        const int R = (l == 0 || !c.compaction) ? c.rows : ld_acquire(&c.cnt[l]);
+        if (R == 0) break;
+        const LayerArgs a = chain_layer_args(c, l, R);
+        wide_pack_body<T>(a, R, blockIdx.x, gridDim.x);
+        if (!grid_barrier(c.bar, gen, c.err, &s_ok)) return;
+        // run_layer_wide returns early only in workgroups with no share of any tile,
+        // which then wait at the barrier below like the others
+        run_layer_wide<T, NT>(a, blockIdx.x, gridDim.x, R);
+        if (!grid_barrier(c.bar, gen, c.err, &s_ok)) return;
+    }
 }
 
 // 16-byte LDS read at an absolute LDS byte address (the offsets already include
@@ -1284,8 +1498,10 @@ __global__ void k_mse_final(const float* partial, int32_t nparts, float* loss, f
 }
 
 // ---------------------------------------------------------------- variant table
-#define SDNN_V(T, NT) {T, NT, 1, (const void*)&k_layer<T, NT, true>, (const void*)&k_chain<T, NT, true>}
-#define SDNN_VD(T, NT) {T, NT, 0, (const void*)&k_layer<T, NT, false>, (const void*)&k_chain<T, NT, false>}
+#define SDNN_V(T, NT) {T, NT, 1, (const void*)&k_layer<T, NT, true>, (const void*)&k_chain<T, NT, true>, nullptr}
+#define SDNN_VD(T, NT) {T, NT, 0, (const void*)&k_layer<T, NT, false>, (const void*)&k_chain<T, NT, false>, nullptr}
+#define SDNN_VW(T, NT) {T, NT, 3, (const void*)&k_layer_wide<T, NT>, (const void*)&k_chain_wide<T, NT>, \
+                        (const void*)&k_wide_pack<T>}
 static const FwdVariant g_variants[] = {
     SDNN_V(1, 256),  SDNN_V(1, 512),  SDNN_V(1, 1024),
     SDNN_V(2, 256),  SDNN_V(2, 512),  SDNN_V(2, 1024),
@@ -1296,10 +1512,14 @@ static const FwdVariant g_variants[] = {
     SDNN_VD(1, 256), SDNN_VD(1, 512), SDNN_VD(1, 1024),
     SDNN_VD(2, 256), SDNN_VD(4, 256),
     {SCHED_T, SCHED_NT, 2, (const void*)&k_layer_sched<SCHED_NT, SCHED_DMAX>,
-     (const void*)&k_chain_sched<SCHED_NT, SCHED_DMAX>},
+     (const void*)&k_chain_sched<SCHED_NT, SCHED_DMAX>, nullptr},
+    SDNN_VW(8, 256),  SDNN_VW(8, 512),
+    SDNN_VW(16, 256), SDNN_VW(16, 512),
+    SDNN_VW(32, 256), SDNN_VW(32, 512),
 };
 #undef SDNN_V
 #undef SDNN_VD
+#undef SDNN_VW
 
 int fwd_variant_count() { return (int)(sizeof(g_variants) / sizeof(g_variants[0])); }
 const void* bwd_dw_sched_fn() { return (const void*)&k_bwd_dw_sched<2 * SCHED_NT, SCHED_DMAX>; }

@@ -45,6 +45,10 @@ struct LayerArgs {
     // w[ent_w[...]] and output row p goes to rows_out[p] (or p)
     const uint32_t* ent_w;
     const int32_t* rows_out;
+    // wide-layer kernels only: packed row tiles [tile][N][T] and two words per tile
+    // (row bits, workgroups done), zero between layers
+    float* packed;
+    int32_t* wide_words;
 };
 
 // Scheduled weight-gradient pass over one layer (rows are compact 0..R-1).
@@ -121,6 +125,9 @@ struct ChainArgs {
     int32_t* prog;
     int32_t parts;
     int32_t nblk;
+    // wide-layer kernels only
+    float* packed;
+    int32_t* wide_words;
 };
 
 // Error codes written to the device error word.
@@ -130,14 +137,21 @@ enum DeviceError : int32_t { DEV_OK = 0, DEV_BARRIER_TIMEOUT = 1 };
 struct FwdVariant {
     int T;          // rows per tile
     int NT;         // threads per workgroup
-    int staged;     // 2 = scheduled resident-weight kernel, 1 = rows staged in LDS, 0 = direct gather
+    int staged;     // 3 = wide (packed row tiles), 2 = scheduled resident-weight kernel,
+                    // 1 = rows staged in LDS, 0 = direct gather
     const void* layer_fn;    // __global__ void(LayerArgs)
     const void* chain_fn;    // __global__ void(ChainArgs)  (cooperative)
+    const void* pack_fn;     // wide only: __global__ void(LayerArgs), launched before layer_fn
 };
+// rows per tile of the wide-layer kernels (the packed buffer and the tile words are
+// sized for the smallest and the largest)
+constexpr int WIDE_TMIN = 8;
+constexpr int WIDE_TMAX = 32;
+constexpr int WIDE_PACK_NT = 256;    // threads of the pack kernel
 int fwd_variant_count();
 const FwdVariant& fwd_variant(int i);
 inline size_t fwd_lds_bytes(const FwdVariant& v, int N) {
-    return v.staged == 2 ? sched_lds_bytes(N) : (v.staged ? (size_t)v.T * N * sizeof(float) : 0);
+    return v.staged == 2 ? sched_lds_bytes(N) : (v.staged == 1 ? (size_t)v.T * N * sizeof(float) : 0);
 }
 
 // Host-side slot scheduling (sdnn_sched.hip): see that file.

@@ -47,6 +47,7 @@ PROTOTYPES = [
     ("sdnn_create", _I32, [ctypes.POINTER(sdnn_desc), _P, _P, _P, _P, _SZ, _P, ctypes.POINTER(_P)]),
     ("sdnn_set_exec", _I32, [_P, _I32]),
     ("sdnn_get_plan", _I32, [_P, ctypes.POINTER(sdnn_plan)]),
+    ("sdnn_set_plan", _I32, [_P, ctypes.POINTER(sdnn_plan)]),
     ("sdnn_set_timing", _I32, [_P, _I32]),
     ("sdnn_kernel_time", _I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I32)]),
     ("sdnn_tune", _I32, [_P, _I64, _P]),
@@ -150,6 +151,11 @@ def sdnn_kernel_time(h):
     return ms.value, n.value
 
 
+def sdnn_set_plan(h, rows_per_tile: int, threads: int, variant: int) -> None:
+    p = sdnn_plan(rows_per_tile=rows_per_tile, threads=threads, grid=0, variant=variant, tuned_us=0.0)
+    _chk(lib().sdnn_set_plan(h, ctypes.byref(p)), "sdnn_set_plan")
+
+
 def sdnn_tune(h, rows: int, stream=None) -> None:
     _chk(lib().sdnn_tune(h, rows, _stream(stream)), "sdnn_tune")
 
@@ -244,6 +250,10 @@ class Net:
 
     def kernel_time(self):
         return sdnn_kernel_time(self.h)
+
+    def set_plan(self, rows_per_tile: int, threads: int, variant: int) -> dict:
+        sdnn_set_plan(self.h, rows_per_tile, threads, variant)
+        return self.plan
 
     def tune(self, rows: int, stream=None) -> dict:
         sdnn_tune(self.h, rows, stream)

@@ -73,6 +73,23 @@ def test_null_arguments_fail_before_any_launch(L):
     assert lib.sdnn_mse(None, None, -1, None, None, None) == L.sdnn.SDNN_EINVAL
 
 
+def test_wide_nets_reserve_the_packed_tiles():
+    """Forward-only nets the scheduled kernel cannot take keep a second copy of the
+    rows (packed tiles of the wide-layer kernels) in the workspace; scheduled and
+    trainable nets do not."""
+    import paper_2004_10908_amd as L
+
+    def per_row(n, flags=0, ckpt=0):
+        a = L.sdnn_workspace_size(L.make_desc(n, 4, 4096, flags=flags, ckpt_every=ckpt))
+        b = L.sdnn_workspace_size(L.make_desc(n, 4, 8192, flags=flags, ckpt_every=ckpt))
+        return (b - a) / 4096
+
+    assert per_row(16384) >= 2 * 16384 * 4
+    assert per_row(6000) >= 2 * 6000 * 4
+    assert per_row(4096) < 2 * 4096 * 4
+    assert per_row(4096, flags=L.sdnn.SDNN_NO_SCHEDULE) < 2 * 4096 * 4
+
+
 def test_no_schedule_flag_shrinks_the_workspace():
     """SDNN_NO_SCHEDULE drops the per-layer schedules from the workspace of a net the
     scheduled kernels would otherwise serve."""
