@@ -490,7 +490,6 @@ def bench_table(args, torch, P, gen, dev):
         trainable = cfg.ckpt_every > 0
         net = P.Net(idx, w, b, max_rows=cfg.rows, ckpt_every=cfg.ckpt_every,
                     flags=P.sdnn.SDNN_TRAINABLE if trainable else 0)
-        net.tune(min(cfg.rows, 8192))
         off = [int(v) for v in gen.make_batches(cfg)] if cfg.n_batches > 1 else None
         o = {}
         net.forward(y0, batch_off=off, out=o, profile=True)
@@ -498,7 +497,7 @@ def bench_table(args, torch, P, gen, dev):
         alg, live = forward_bytes(prof, N, L), live_edges(prof, N, L)
         steps = 1 if L * N > 480 * 16384 else 3
         r = {"rows": cfg.rows, "N": N, "layers": L, "alive_head": [int(v) for v in prof[:4]],
-             "alive_last": int(prof[L]), "alg_bytes": alg}
+             "alive_last": int(prof[L]), "alg_bytes": alg, "plan": net.plan}
         forms = [("plain", "graph")] + ([("merged", "graph_merged"), ("persistent", "persistent")] if off else
                                         [("persistent", "persistent")])
         for form, eng in forms:

@@ -54,7 +54,7 @@ constexpr size_t LDS_BUDGET = 160 * 1024;       // dynamic LDS a workgroup may u
 constexpr int MSE_BLOCKS = 256;
 constexpr int SCHED_GRID = 256;                 // workgroups of the scheduled kernels (8 XCDs x 32)
 constexpr int WIDE_DEFAULT_T = 32;               // default tile of the wide-layer kernels (before tuning)
-constexpr int WIDE_DEFAULT_NT = 512;
+constexpr int WIDE_DEFAULT_NT = 1024;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
@@ -319,10 +319,12 @@ int default_variant(const sdnn_net_s* n) {
         if (v.NT != want_nt) continue;
         if (v.T > bestT) { bestT = v.T; best = i; }
     }
-    // a row tile of 2 or more rows in LDS beats the packed tiles (16384 neurons: 15.6
-    // against 24.4 ms per 60000-row layer); with no LDS tile the packed tiles win by
-    // about 15x over 4-byte gathers straight from the rows (65536 neurons)
-    if (n->wide && best < 0)
+    // where not even 2 rows fit LDS the packed tiles win by far (65536 neurons: 16.0
+    // ms per 15000-row layer against 315 ms for 4-byte gathers straight from the
+    // rows).  At 16384 neurons they are ahead on a full-live layer (13.6 against 15.6
+    // ms per 60000-row layer) but behind on the whole forward, where every empty
+    // layer costs them two launches (pack and compute) instead of one
+    if (n->wide && bestT < 2)
         for (int i = 0; i < fwd_variant_count(); ++i) {
             const FwdVariant& v = fwd_variant(i);
             if (v.staged == 3 && v.T == WIDE_DEFAULT_T && v.NT == WIDE_DEFAULT_NT) return i;

@@ -1516,6 +1516,7 @@ static const FwdVariant g_variants[] = {
     SDNN_VW(8, 256),  SDNN_VW(8, 512),
     SDNN_VW(16, 256), SDNN_VW(16, 512),
     SDNN_VW(32, 256), SDNN_VW(32, 512),
+    SDNN_VW(16, 1024), SDNN_VW(32, 1024),
 };
 #undef SDNN_V
 #undef SDNN_VD

@@ -13,7 +13,7 @@ from tests.sdnn_gpu import DEV, check_end_to_end, check_layer_sync, host_layers,
 pytestmark = pytest.mark.gpu
 
 MODES = ["eager", "graph", "persistent", "graph_merged"]
-WIDE = [(T, NT, 3) for T in (8, 16, 32) for NT in (256, 512)]
+WIDE = [(T, NT, 3) for T in (8, 16, 32) for NT in (256, 512)] + [(16, 1024, 3), (32, 1024, 3)]
 
 
 @pytest.fixture(scope="module")
@@ -35,11 +35,11 @@ def test_wide_forward_matches_oracle(P, N, layers, rows):
     ref = oracle.forward(host_layers(idx, w, b), y0h, cfg.clamp, bound=True)
     y0 = torch.from_numpy(y0h).to(DEV)
     net = P.Net(idx, w, b, max_rows=rows)
-    if N * 4 > 160 * 1024:
-        assert net.plan["variant"] == 3, net.plan    # no LDS row tile fits: the wide kernel is the default
+    if 2 * N * 4 > 160 * 1024:
+        assert net.plan["variant"] == 3, net.plan    # not even 2 LDS rows fit: the wide kernel is the default
     else:
-        assert net.plan["variant"] == 0, net.plan    # an LDS row tile is faster where one fits
-        net.set_plan(32, 512, 3)
+        assert net.plan["variant"] == 0, net.plan    # LDS row tiles where 2 or more fit
+        net.set_plan(32, 1024, 3)
     base = None
     for m in MODES:
         o, nz = run_forward(net, y0, mode=m)
