@@ -319,8 +319,8 @@ __global__ __launch_bounds__(NT) void k_chain(ChainArgs c) {
 }
 
 // ---------------------------------------------------------------- wide-layer kernels
-// For layers too wide for a tile of several rows in LDS (the 65536- and
-// 16384-neuron nets), a layer is two passes:
+// For layers too wide for a tile of several rows in LDS (by default where not even
+// 2 rows fit, e.g. 65536 neurons), a layer is two passes:
 //  * pack: the rows of the work list, T at a time, are copied into a workspace
 //    buffer as tiles [tile][N][T], so the T values of one input id are contiguous;
 //  * compute: a gather of input id i is then T * 4 contiguous bytes serving T rows,
@@ -328,9 +328,10 @@ __global__ __launch_bounds__(NT) void k_chain(ChainArgs c) {
 //    (4 rows) each, so one load instruction reads whole slots.  Tile X goes to
 //    workgroup group X % 8 (group = blockIdx % 8, the XCD it runs on); the
 //    workgroups of a group split each of its tiles by chunks of 4 NT / T neurons
-//    (their 32 (id, weight) pairs read per tile), so a tile is fetched into that
-//    XCD's L2 once and gathered from there by all of them.  A group with at least
-//    twice as many workgroups as chunks runs several tile sub-streams.
+//    (their 32 (id, weight) pairs read per tile), so the gathers from a tile all
+//    go through one XCD's L2 (a tile larger than the L2, 32 rows of 65536 floats,
+//    is served from the Infinity Cache).  A group with at least twice as many
+//    workgroups as chunks runs several tile sub-streams.
 //    The last workgroup to finish a tile (a counter per tile) publishes its row
 //    liveness: list slots, alive flags, dead rows zeroed where asked.
 // The per-output arithmetic is run_layer's (slots in ascending order with fused
