@@ -66,7 +66,8 @@ typedef enum {
                                     streamed through device slots */
 
 /* sdnn_set_exec modes */
-#define SDNN_EXEC_AUTO         0 /* GRAPH for one batch, GRAPH_MERGED for several */
+#define SDNN_EXEC_AUTO         0 /* GRAPH for one batch, GRAPH_MERGED for several; PERSISTENT
+                                    on the wide-layer kernels (plan variant 3) */
 #define SDNN_EXEC_EAGER        1 /* one kernel launch per layer, batches one after another */
 #define SDNN_EXEC_GRAPH        2 /* one hipGraph; batches one after another ("plain" form) */
 #define SDNN_EXEC_PERSISTENT   3 /* all layers of all batches in one cooperative kernel ("batched") */
