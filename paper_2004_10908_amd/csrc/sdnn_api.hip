@@ -59,7 +59,7 @@ constexpr int WIDE_DEFAULT_NT = 1024;
 size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Layout {
-    size_t act = 0, list0 = 0, list1 = 0, alive = 0, cnt = 0, bar = 0, err = 0, flag = 0;
+    size_t act = 0, list0 = 0, list1 = 0, alive = 0, cnt = 0, bar = 0, err = 0, flag = 0, fin = 0;
     size_t ent = 0, lane_neuron = 0, wave_steps = 0, tile_bits = 0, prog = 0;
     size_t ent_t = 0, ent_w = 0, lane_input = 0, steps_t = 0, gbuf2 = 0;
     bool sched = false;
@@ -129,6 +129,7 @@ Layout make_layout(const sdnn_desc& d) {
         y.wide_words = take(2 * ((R + WIDE_TMIN - 1) / WIDE_TMIN) * 4);
     }
     y.bar = take(NBAR * 4);
+    y.fin = take(FIN_BLOCKS * 4);
     y.err = take(64);
     y.flag = take(64);
     if (trainable(d)) {
@@ -220,6 +221,7 @@ struct sdnn_net_s {
     Layout lay;
     float* act = nullptr;
     int32_t *list0 = nullptr, *list1 = nullptr, *alive = nullptr, *cnt = nullptr, *err = nullptr, *flag = nullptr;
+    int32_t* fin = nullptr;             // per-range alive counts of the finalize passes
     unsigned* bar = nullptr;
     int32_t *tr_ptr = nullptr, *tr_e = nullptr;
     float *seg = nullptr, *gbuf0 = nullptr, *gbuf1 = nullptr, *pdw = nullptr, *pdb = nullptr;
@@ -436,6 +438,17 @@ LayerArgs layer_args_chain(const sdnn_net_s* n, int l, const float* y0, float* y
     return a;
 }
 
+// The two finalize passes: alive rows per row range, then the ascending nonzero-row
+// ids and the per-layer row profile (summed over `regions` count regions).
+void push_finalize(Plan& p, const sdnn_net_s* n, int64_t rows, int32_t* nz_rows, int32_t* n_nz, int regions,
+                   int32_t* layer_rows) {
+    p.push_back(mk((const void*)&k_fin_count, dim3(FIN_BLOCKS), dim3(1024), 0, (const int32_t*)n->alive, (int32_t)rows,
+                   n->fin));
+    p.push_back(mk((const void*)&k_fin_write, dim3(FIN_BLOCKS), dim3(1024), 0, (const int32_t*)n->alive, (int32_t)rows,
+                   (const int32_t*)n->fin, nz_rows, n_nz, (const int32_t*)n->cnt, (int32_t)regions,
+                   (int32_t)n->d.n_layers, layer_rows));
+}
+
 // The per-batch ("plain") chain: for each non-empty batch, an init node and L
 // layer nodes; then one finalize node.  Used eagerly or as one hipGraph.
 Plan plan_chain(const sdnn_net_s* n, const float* y0, int64_t rows, const int64_t* off, int nb, float* y_out,
@@ -458,8 +471,7 @@ Plan plan_chain(const sdnn_net_s* n, const float* y0, int64_t rows, const int64_
         }
         ++region;
     }
-    p.push_back(mk((const void*)&k_finalize, dim3(1), dim3(1024), 0, (const int32_t*)n->alive, (int32_t)rows, nz_rows,
-                   n_nz, (const int32_t*)n->cnt, (int32_t)region, (int32_t)L, layer_rows));
+    push_finalize(p, n, rows, nz_rows, n_nz, region, layer_rows);
     return p;
 }
 
@@ -513,8 +525,7 @@ Plan plan_persistent(const sdnn_net_s* n, const float* y0, int64_t rows, float* 
     ch->cooperative = true;
     ch->timed = true;
     p.push_back(std::move(ch));
-    p.push_back(mk((const void*)&k_finalize, dim3(1), dim3(1024), 0, (const int32_t*)n->alive, (int32_t)rows, nz_rows,
-                   n_nz, (const int32_t*)n->cnt, (int32_t)1, (int32_t)L, layer_rows));
+    push_finalize(p, n, rows, nz_rows, n_nz, 1, layer_rows);
     return p;
 }
 
@@ -631,6 +642,7 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
     n->alive = (int32_t*)(n->ws + lay.alive);
     n->cnt = (int32_t*)(n->ws + lay.cnt);
     n->bar = (unsigned*)(n->ws + lay.bar);
+    n->fin = (int32_t*)(n->ws + lay.fin);
     n->err = (int32_t*)(n->ws + lay.err);
     n->flag = (int32_t*)(n->ws + lay.flag);
     if (trainable(*desc)) {

@@ -227,45 +227,79 @@ __device__ bool grid_barrier(unsigned* bar, unsigned& gen, int32_t* err, int* s_
 
 // ---------------------------------------------------------------- finalize
 // Ascending ids of rows whose final activations are nonzero, and the per-layer
-// row profile.  One workgroup of 1024 threads: each thread counts a contiguous
-// segment of rows, an exclusive scan gives each segment its output offset.
+// row profile.  Two passes of FIN_BLOCKS workgroups over consecutive row ranges:
+// k_fin_count counts each range's alive rows (coalesced loads); k_fin_write gives
+// each range its output offset (the sum of the ranges before it) and writes its
+// rows in ascending order, 1024 at a time, each wave placing its rows with a
+// ballot and the waves in order through LDS.
 constexpr int FIN_NT = 1024;
 
-__device__ void finalize_body(const int32_t* alive, int32_t rows, int32_t* nz_rows, int32_t* n_nz, const int32_t* cnt,
-                              int32_t n_regions, int32_t L, int32_t* layer_rows) {
-    __shared__ int32_t s_scan[FIN_NT];
-    const int tid = threadIdx.x;
-    const int seg = (rows + FIN_NT - 1) / FIN_NT;
-    const int r0 = min(rows, tid * seg), r1 = min(rows, r0 + seg);
+__device__ __forceinline__ void fin_range(int32_t rows, int64_t* r0, int64_t* r1) {
+    const int64_t per = ((int64_t)rows + FIN_BLOCKS - 1) / FIN_BLOCKS;
+    *r0 = min((int64_t)rows, (int64_t)blockIdx.x * per);
+    *r1 = min((int64_t)rows, *r0 + per);
+}
+
+__global__ __launch_bounds__(FIN_NT) void k_fin_count(const int32_t* alive, int32_t rows, int32_t* part) {
+    __shared__ int s_w[FIN_NT / 64];
+    int64_t r0, r1;
+    fin_range(rows, &r0, &r1);
     int c = 0;
-    for (int r = r0; r < r1; ++r) c += alive[r] != 0;
-    s_scan[tid] = c;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += FIN_NT) c += alive[r] != 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = c;
     __syncthreads();
-    for (int off = 1; off < FIN_NT; off <<= 1) {
-        const int v = tid >= off ? s_scan[tid - off] : 0;
-        __syncthreads();
-        s_scan[tid] += v;
-        __syncthreads();
-    }
-    int pos = s_scan[tid] - c;
-    for (int r = r0; r < r1; ++r)
-        if (alive[r] != 0) nz_rows[pos++] = r;
-    const int total = s_scan[FIN_NT - 1];
-    if (tid == 0) *n_nz = total;
-    if (layer_rows) {
-        for (int l = tid; l < L; l += FIN_NT) {
-            int s = 0;
-            for (int g = 0; g < n_regions; ++g) s += cnt[(size_t)g * (L + 1) + l];
-            layer_rows[l] = s;
-        }
-        if (tid == 0) layer_rows[L] = total;
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < FIN_NT / 64; ++w) t += s_w[w];
+        part[blockIdx.x] = t;
     }
 }
 
-__global__ __launch_bounds__(FIN_NT) void k_finalize(const int32_t* alive, int32_t rows, int32_t* nz_rows,
-                                                     int32_t* n_nz, const int32_t* cnt, int32_t n_regions, int32_t L,
-                                                     int32_t* layer_rows) {
-    finalize_body(alive, rows, nz_rows, n_nz, cnt, n_regions, L, layer_rows);
+__global__ __launch_bounds__(FIN_NT) void k_fin_write(const int32_t* alive, int32_t rows, const int32_t* part,
+                                                      int32_t* nz_rows, int32_t* n_nz, const int32_t* cnt,
+                                                      int32_t n_regions, int32_t L, int32_t* layer_rows) {
+    __shared__ int s_w[FIN_NT / 64];
+    __shared__ int s_base;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int64_t r0, r1;
+    fin_range(rows, &r0, &r1);
+    if (tid == 0) {
+        int b = 0;
+        for (int i = 0; i < (int)blockIdx.x; ++i) b += part[i];
+        s_base = b;
+        if (blockIdx.x == 0) {
+            int total = 0;
+            for (int i = 0; i < FIN_BLOCKS; ++i) total += part[i];
+            *n_nz = total;
+            if (layer_rows) layer_rows[L] = total;
+        }
+    }
+    if (blockIdx.x == 0 && layer_rows) {
+        for (int l = tid; l < L; l += FIN_NT) {
+            int sum = 0;
+            for (int g = 0; g < n_regions; ++g) sum += cnt[(size_t)g * (L + 1) + l];
+            layer_rows[l] = sum;
+        }
+    }
+    __syncthreads();
+    int base = s_base;
+    for (int64_t rc = r0; rc < r1; rc += FIN_NT) {
+        const int64_t r = rc + tid;
+        const bool f = r < r1 && alive[r] != 0;
+        const unsigned long long m = __ballot(f);
+        if (lane == 0) s_w[wave] = __popcll(m);
+        __syncthreads();
+        int woff = 0, tot = 0;
+        for (int w = 0; w < FIN_NT / 64; ++w) {
+            woff += w < wave ? s_w[w] : 0;
+            tot += s_w[w];
+        }
+        if (f) nz_rows[base + woff + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)r;
+        base += tot;
+        __syncthreads();                           // s_w is rewritten next round
+    }
 }
 
 // ---------------------------------------------------------------- persistent chain
@@ -315,7 +349,7 @@ __global__ __launch_bounds__(NT) void k_chain(ChainArgs c) {
         run_layer<T, NT, STAGED>(a, lds, blockIdx.x, gridDim.x, R);
         if (!grid_barrier(c.bar, gen, c.err, &s_ok)) return;
     }
-    // the nz list and the row profile are produced by a k_finalize launch after this kernel
+    // the nz list and the row profile are produced by the finalize passes after this kernel
 }
 
 // ---------------------------------------------------------------- wide-layer kernels

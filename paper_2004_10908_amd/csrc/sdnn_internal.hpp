@@ -162,8 +162,10 @@ int build_transposed_schedule(const int32_t* idx, int N, int L, int dmax, uint32
 
 // Small kernels (sdnn_fwd.hip).
 __global__ void k_chain_init(int32_t* cnt, int32_t L, int32_t rows, int32_t compaction, unsigned* bar, int32_t nbar);
-__global__ void k_finalize(const int32_t* alive, int32_t rows, int32_t* nz_rows, int32_t* n_nz, const int32_t* cnt,
-                           int32_t n_regions, int32_t L, int32_t* layer_rows);
+constexpr int FIN_BLOCKS = 64;   // workgroups of the finalize passes (each a consecutive row range)
+__global__ void k_fin_count(const int32_t* alive, int32_t rows, int32_t* part);
+__global__ void k_fin_write(const int32_t* alive, int32_t rows, const int32_t* part, int32_t* nz_rows, int32_t* n_nz,
+                            const int32_t* cnt, int32_t n_regions, int32_t L, int32_t* layer_rows);
 __global__ void k_fill_f32(float* p, int64_t n, float v);
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v);
 __global__ void k_check_params(const int32_t* idx, const float* w, const float* b, int32_t N, int32_t L,
