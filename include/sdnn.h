@@ -232,7 +232,9 @@ sdnn_status sdnn_mse(const float *y, const float *t, int64_t n, float *dy, float
 int32_t sdnn_schedule_host(const int32_t *idx, int32_t n_neurons, int32_t n_layers, int32_t dmax, uint32_t *ent,
                            int32_t *lane_neuron, int32_t *steps);
 
-/* Synchronize `stream` and report whether a kernel of this net raised its error word. */
+/* Synchronize `stream` and report whether a kernel of this net raised its error word.
+ * The word stays set: after SDNN_EDEVICE the net's scratch state (work lists, per-tile
+ * counters of a layer that stopped part-way) is undefined, so destroy and recreate it. */
 sdnn_status sdnn_check_device(sdnn_net net, void *stream);
 
 /* Release the net (NULL-safe).  Does not free caller buffers. */
