@@ -413,13 +413,19 @@ __global__ __launch_bounds__(WIDE_PACK_NT) void k_wide_pack(LayerArgs a) {
     wide_pack_body<T>(a, R, blockIdx.x, gridDim.x);
 }
 
-// slot groups (4 slots each) whose gathers the compiler may keep in flight together
-constexpr int WIDE_UNROLL = 4;
+// slot groups (4 slots each) whose gathers the compiler may keep in flight together.
+// Layer kernel at 1024 threads: one group (56 VGPRs) lets two workgroups share a CU,
+// which beat four groups with one workgroup per CU (C4 layer 15.2 against 15.9 ms);
+// at 512 threads four groups are faster (20.3 against 26.6 ms).  The persistent chain
+// holds one 1024-thread workgroup per CU either way (its pack and barrier code need
+// more registers), so it keeps four groups (C4 forward 29.0 against 33.2 ms).
+template <int NT, bool CHAIN>
+constexpr int wide_unroll() { return (NT >= 1024 && !CHAIN) ? 1 : 4; }
 
 // The Q = T / 4 lanes of one neuron split the tile's rows, 4 each: lane quarter rq
 // reads bytes 16 rq .. 16 rq + 15 of the T * 4-byte slot, so one load instruction
 // fetches 64 / Q whole slots (contiguous segments) rather than 64 scattered pieces.
-template <int T, int NT>
+template <int T, int NT, int UNROLL>
 __device__ __forceinline__ void run_layer_wide(const LayerArgs& a, int wg, int nwg, int R) {
     static_assert(T % 4 == 0 && T <= 32, "T rows must fit the 32 row bits of a tile word");
     constexpr int Q = T / 4;                       // lanes per neuron
@@ -467,7 +473,7 @@ __device__ __forceinline__ void run_layer_wide(const LayerArgs& a, int wg, int n
                 };
                 const int4* ip = reinterpret_cast<const int4*>(a.idx + (size_t)j * K);
                 const float4* wp = reinterpret_cast<const float4*>(a.w + (size_t)j * K);
-#pragma unroll WIDE_UNROLL
+#pragma unroll UNROLL
                 for (int q = 0; q < K / 4; ++q) {
                     const int4 iv = ip[q];
                     const float4 wv = wp[q];
@@ -539,7 +545,7 @@ __device__ __forceinline__ void run_layer_wide(const LayerArgs& a, int wg, int n
 template <int T, int NT>
 __global__ __launch_bounds__(NT) void k_layer_wide(LayerArgs a) {
     const int R = a.cnt_in ? *a.cnt_in : a.nrows;
-    run_layer_wide<T, NT>(a, blockIdx.x, gridDim.x, R);
+    run_layer_wide<T, NT, wide_unroll<NT, false>()>(a, blockIdx.x, gridDim.x, R);
 }
 
 // Persistent chain of the wide kernels: pack, grid barrier, compute, grid barrier.
@@ -555,7 +561,7 @@ __global__ __launch_bounds__(NT) void k_chain_wide(ChainArgs c) {
         if (!grid_barrier(c.bar, gen, c.err, &s_ok)) return;
         // run_layer_wide returns early only in workgroups with no share of any tile,
         // which then wait at the barrier below like the others
-        run_layer_wide<T, NT>(a, blockIdx.x, gridDim.x, R);
+        run_layer_wide<T, NT, wide_unroll<NT, true>()>(a, blockIdx.x, gridDim.x, R);
         if (!grid_barrier(c.bar, gen, c.err, &s_ok)) return;
     }
 }
