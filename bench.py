@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-extras", dest="extras", action="store_false")
     ap.add_argument("--cpu", dest="cpu", action="store_true", default=True)
     ap.add_argument("--no-cpu", dest="cpu", action="store_false")
-    ap.add_argument("--cpu-rows", type=int, default=3000, help="row sample for the oracle baseline")
+    ap.add_argument("--cpu-rows", type=int, default=15000, help="row sample for the oracle baseline (about 12 s)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (the reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale) and exit")
