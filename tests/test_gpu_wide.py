@@ -12,7 +12,7 @@ from tests.sdnn_gpu import DEV, check_end_to_end, check_layer_sync, host_layers,
 
 pytestmark = pytest.mark.gpu
 
-MODES = ["eager", "graph", "persistent", "graph_merged"]
+MODES = ["eager", "graph", "persistent", "graph_merged", "auto"]   # auto: persistent on the wide kernels
 WIDE = [(T, NT, 3) for T in (8, 16, 32) for NT in (256, 512)] + [(16, 1024, 3), (32, 1024, 3)]
 
 
