@@ -234,8 +234,20 @@ int32_t sdnn_schedule_host(const int32_t *idx, int32_t n_neurons, int32_t n_laye
 
 /* Synchronize `stream` and report whether a kernel of this net raised its error word.
  * The word stays set: after SDNN_EDEVICE the net's scratch state (work lists, per-tile
- * counters of a layer that stopped part-way) is undefined, so destroy and recreate it. */
+ * counters of a layer that stopped part-way) is undefined, so destroy and recreate it.
+ * Without a synchronization, the finalize pass of every sdnn_forward copies a raised
+ * error word into pinned host memory, and sdnn_forward, sdnn_layer, sdnn_backward,
+ * sdnn_layer_backward and sdnn_tune return SDNN_EDEVICE (launching nothing) once that
+ * copy has landed, i.e. on the first call that starts after the failing forward has
+ * finished on the device. */
 sdnn_status sdnn_check_device(sdnn_net net, void *stream);
+
+/* Failure injection for tests of the error path: enqueue on `stream` a write of `code`
+ * (nonzero) into the net's device error word, as a timed-out barrier would.  Every
+ * persistent-kernel grid barrier then gives up at once (its kernel returns normally),
+ * the next forward's finalize pass publishes the word, and the net must be recreated.
+ * SDNN_EINVAL for a NULL net or code 0. */
+sdnn_status sdnn_inject_device_error(sdnn_net net, int32_t code, void *stream);
 
 /* Release the net (NULL-safe).  Does not free caller buffers. */
 void sdnn_destroy(sdnn_net net);

@@ -222,6 +222,8 @@ struct sdnn_net_s {
     float* act = nullptr;
     int32_t *list0 = nullptr, *list1 = nullptr, *alive = nullptr, *cnt = nullptr, *err = nullptr, *flag = nullptr;
     int32_t* fin = nullptr;             // per-range alive counts of the finalize passes
+    int32_t* herr = nullptr;            // pinned host word: the device error as the finalize pass published it
+    int32_t* herr_dev = nullptr;        // its device address
     unsigned* bar = nullptr;
     int32_t *tr_ptr = nullptr, *tr_e = nullptr;
     float *seg = nullptr, *gbuf0 = nullptr, *gbuf1 = nullptr, *pdw = nullptr, *pdb = nullptr;
@@ -250,11 +252,23 @@ struct sdnn_net_s {
     bool timing = false;                 // sdnn_set_timing
     std::vector<hipEvent_t> tev;         // start/stop pairs, created on first use
     size_t tev_used = 0;                 // events recorded since the last sdnn_kernel_time
+    ~sdnn_net_s() {
+        if (herr) (void)hipHostFree(herr);
+    }
 };
 
 namespace {
 
 const FwdVariant& var(const sdnn_net_s* n) { return fwd_variant(n->variant); }
+
+// SDNN_EDEVICE if a kernel of an earlier call raised the device error word and the
+// finalize pass of a forward (or sdnn_check_device) has published it to the host.
+sdnn_status host_error(const sdnn_net_s* n) {
+    const int32_t e = n->herr ? __atomic_load_n(n->herr, __ATOMIC_ACQUIRE) : 0;
+    if (e == DEV_BARRIER_TIMEOUT) return fail(SDNN_EDEVICE, "a persistent-kernel grid barrier timed out in an earlier call");
+    if (e != 0) return fail(SDNN_EDEVICE, "device error %d raised in an earlier call", e);
+    return SDNN_OK;
+}
 
 bool variant_fits(const sdnn_net_s* n, const FwdVariant& v) {
     if (v.staged == 3) return n->wide;
@@ -420,7 +434,7 @@ LayerArgs layer_args_chain(const sdnn_net_s* n, int l, const float* y0, float* y
     a.yin = l == 0 ? y0 : (out_is_y ? n->act : y_out);
     a.yout = out_is_y ? y_out : n->act;
     a.ycopy = (ckpt && S > 0 && (l + 1) % S == 0 && l + 1 < L) ? ckpt + (size_t)((l + 1) / S - 1) * rows * N : nullptr;
-    a.yzero = (cmp && !out_is_y) ? y_out : nullptr;
+    a.dead_mark = (cmp && !out_is_y) ? -1 : 0;
     a.idx = n->idx + l * NK;
     a.w = n->w + l * NK;
     a.b = n->b + (size_t)l * N;
@@ -438,15 +452,19 @@ LayerArgs layer_args_chain(const sdnn_net_s* n, int l, const float* y0, float* y
     return a;
 }
 
-// The two finalize passes: alive rows per row range, then the ascending nonzero-row
-// ids and the per-layer row profile (summed over `regions` count regions).
-void push_finalize(Plan& p, const sdnn_net_s* n, int64_t rows, int32_t* nz_rows, int32_t* n_nz, int regions,
-                   int32_t* layer_rows) {
+// The finalize passes: alive rows per row range, then the ascending nonzero-row
+// ids and the per-layer row profile (summed over `regions` count regions), then the
+// clearing of rows that died while the output buffer held their older values.
+void push_finalize(Plan& p, const sdnn_net_s* n, int64_t rows, float* y_out, int32_t* nz_rows, int32_t* n_nz,
+                   int regions, int32_t* layer_rows) {
     p.push_back(mk((const void*)&k_fin_count, dim3(FIN_BLOCKS), dim3(1024), 0, (const int32_t*)n->alive, (int32_t)rows,
                    n->fin));
     p.push_back(mk((const void*)&k_fin_write, dim3(FIN_BLOCKS), dim3(1024), 0, (const int32_t*)n->alive, (int32_t)rows,
                    (const int32_t*)n->fin, nz_rows, n_nz, (const int32_t*)n->cnt, (int32_t)regions,
-                   (int32_t)n->d.n_layers, layer_rows));
+                   (int32_t)n->d.n_layers, layer_rows, (const int32_t*)n->err, n->herr_dev));
+    if (n->compaction && rows > 0)
+        p.push_back(mk((const void*)&k_fin_zero, dim3((unsigned)std::min<int64_t>(rows, 2048)), dim3(256), 0,
+                       (const int32_t*)n->alive, (int32_t)rows, (int32_t)n->d.n_neurons, y_out));
 }
 
 // The per-batch ("plain") chain: for each non-empty batch, an init node and L
@@ -471,7 +489,7 @@ Plan plan_chain(const sdnn_net_s* n, const float* y0, int64_t rows, const int64_
         }
         ++region;
     }
-    push_finalize(p, n, rows, nz_rows, n_nz, region, layer_rows);
+    push_finalize(p, n, rows, y_out, nz_rows, n_nz, region, layer_rows);
     return p;
 }
 
@@ -525,7 +543,7 @@ Plan plan_persistent(const sdnn_net_s* n, const float* y0, int64_t rows, float* 
     ch->cooperative = true;
     ch->timed = true;
     p.push_back(std::move(ch));
-    push_finalize(p, n, rows, nz_rows, n_nz, 1, layer_rows);
+    push_finalize(p, n, rows, y_out, nz_rows, n_nz, 1, layer_rows);
     return p;
 }
 
@@ -661,6 +679,20 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
     }
     HIPCHK(hipGetDevice(&n->device));
     HIPCHK(hipDeviceGetAttribute(&n->num_cu, hipDeviceAttributeMultiprocessorCount, n->device));
+    {
+        void* h = nullptr;
+        HIPCHK(hipHostMalloc(&h, 64, hipHostMallocMapped));
+        n->herr = (int32_t*)h;
+        *n->herr = 0;
+        void* hd = nullptr;
+        const hipError_t e = hipHostGetDevicePointer(&hd, h, 0);
+        if (e != hipSuccess) {
+            (void)hipHostFree(h);
+            n->herr = nullptr;
+            return fail(SDNN_EHIP, "hipHostGetDevicePointer failed: %s", hipGetErrorString(e));
+        }
+        n->herr_dev = (int32_t*)hd;
+    }
 
     const int N = desc->n_neurons, L = desc->n_layers;
     const int64_t nnz = (int64_t)N * K * L;
@@ -865,6 +897,7 @@ sdnn_status sdnn_set_plan(sdnn_net net, const sdnn_plan* plan) {
 
 sdnn_status sdnn_tune(sdnn_net net, int64_t rows, void* stream) {
     if (!net) return fail(SDNN_EINVAL, "net is NULL");
+    TRY(host_error(net));
     hipStream_t s = (hipStream_t)stream;
     const int N = net->d.n_neurons;
     const int64_t rt = std::min<int64_t>(rows, net->d.max_rows / 2);
@@ -927,6 +960,7 @@ sdnn_status sdnn_forward(sdnn_net net, const float* y0, int64_t rows, const int6
                          float* y_out, int32_t* nz_rows, int32_t* n_nz, float* ckpt, int32_t* layer_rows,
                          void* stream) {
     if (!net) return fail(SDNN_EINVAL, "net is NULL");
+    TRY(host_error(net));
     const sdnn_desc& d = net->d;
     if (rows < 0 || rows > d.max_rows) return fail(SDNN_EINVAL, "rows = %lld outside [0, max_rows = %lld]",
                                                   (long long)rows, (long long)d.max_rows);
@@ -990,6 +1024,7 @@ sdnn_status sdnn_forward(sdnn_net net, const float* y0, int64_t rows, const int6
 
 sdnn_status sdnn_layer(sdnn_net net, int32_t layer, const float* y_in, int64_t rows, float* y_out, void* stream) {
     if (!net) return fail(SDNN_EINVAL, "net is NULL");
+    TRY(host_error(net));
     const sdnn_desc& d = net->d;
     if (layer < 0 || layer >= d.n_layers) return fail(SDNN_EINVAL, "layer %d out of range", layer);
     if (rows < 0 || rows > d.max_rows) return fail(SDNN_EINVAL, "rows = %lld outside [0, max_rows = %lld]",
@@ -1020,6 +1055,7 @@ sdnn_status sdnn_backward(sdnn_net net, const float* y0, int64_t rows, const flo
                           const int32_t* n_nz, const float* dy_out, float* dw, float* dbias, float* dy0,
                           void* stream) {
     if (!net) return fail(SDNN_EINVAL, "net is NULL");
+    TRY(host_error(net));
     const sdnn_desc& d = net->d;
     if (!trainable(d)) return fail(SDNN_EINVAL, "net was not created with SDNN_TRAINABLE");
     if (rows < 0 || rows > d.max_rows) return fail(SDNN_EINVAL, "rows out of range");
@@ -1119,6 +1155,7 @@ sdnn_status sdnn_layer_backward(sdnn_net net, int32_t layer, const float* y_in, 
                                 const float* dy_out, int64_t rows, float* dw, float* dbias, float* dy_in,
                                 void* stream) {
     if (!net) return fail(SDNN_EINVAL, "net is NULL");
+    TRY(host_error(net));
     const sdnn_desc& d = net->d;
     if (!trainable(d)) return fail(SDNN_EINVAL, "net was not created with SDNN_TRAINABLE");
     if (layer < 0 || layer >= d.n_layers) return fail(SDNN_EINVAL, "layer %d out of range", layer);
@@ -1204,8 +1241,17 @@ sdnn_status sdnn_check_device(sdnn_net net, void* stream) {
     int32_t e = 0;
     HIPCHK(hipMemcpyAsync(&e, net->err, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (e != 0 && net->herr) __atomic_store_n(net->herr, e, __ATOMIC_RELEASE);
     if (e == DEV_BARRIER_TIMEOUT) return fail(SDNN_EDEVICE, "a persistent-kernel grid barrier timed out");
     if (e != 0) return fail(SDNN_EDEVICE, "device error %d", e);
+    return SDNN_OK;
+}
+
+sdnn_status sdnn_inject_device_error(sdnn_net net, int32_t code, void* stream) {
+    if (!net) return fail(SDNN_EINVAL, "net is NULL");
+    if (code == 0) return fail(SDNN_EINVAL, "code must be nonzero");
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, (hipStream_t)stream, net->err, (int64_t)1, code);
+    HIPCHK(hipGetLastError());
     return SDNN_OK;
 }
 

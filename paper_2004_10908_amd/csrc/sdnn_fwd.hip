@@ -154,16 +154,7 @@ __device__ __forceinline__ void run_layer(const LayerArgs& a, float* __restrict_
         }
         if (a.alive && tid < T) {
             const int r = s_rows[tid];
-            if (r >= 0) a.alive[r] = (int32_t)((alive >> tid) & 1u);
-        }
-        if (a.yzero) {
-#pragma unroll
-            for (int t = 0; t < T; ++t) {
-                if (rr[t] >= 0 && !((alive >> t) & 1u)) {
-                    float* z = a.yzero + (size_t)rr[t] * N;
-                    for (int i = tid; i < N; i += NT) z[i] = 0.f;
-                }
-            }
+            if (r >= 0) a.alive[r] = ((alive >> tid) & 1u) ? 1 : a.dead_mark;
         }
         __syncthreads();
     }
@@ -245,7 +236,7 @@ __global__ __launch_bounds__(FIN_NT) void k_fin_count(const int32_t* alive, int3
     int64_t r0, r1;
     fin_range(rows, &r0, &r1);
     int c = 0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += FIN_NT) c += alive[r] != 0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += FIN_NT) c += alive[r] > 0;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
     if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = c;
@@ -259,7 +250,8 @@ __global__ __launch_bounds__(FIN_NT) void k_fin_count(const int32_t* alive, int3
 
 __global__ __launch_bounds__(FIN_NT) void k_fin_write(const int32_t* alive, int32_t rows, const int32_t* part,
                                                       int32_t* nz_rows, int32_t* n_nz, const int32_t* cnt,
-                                                      int32_t n_regions, int32_t L, int32_t* layer_rows) {
+                                                      int32_t n_regions, int32_t L, int32_t* layer_rows,
+                                                      const int32_t* err, int32_t* host_err) {
     __shared__ int s_w[FIN_NT / 64];
     __shared__ int s_base;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -274,6 +266,10 @@ __global__ __launch_bounds__(FIN_NT) void k_fin_write(const int32_t* alive, int3
             for (int i = 0; i < FIN_BLOCKS; ++i) total += part[i];
             *n_nz = total;
             if (layer_rows) layer_rows[L] = total;
+            // a device error raised by this forward (or injected) becomes visible to the
+            // host without a synchronization: the library's next call reports it
+            const int32_t e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (e != 0 && host_err) __hip_atomic_store(host_err, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
     if (blockIdx.x == 0 && layer_rows) {
@@ -287,7 +283,7 @@ __global__ __launch_bounds__(FIN_NT) void k_fin_write(const int32_t* alive, int3
     int base = s_base;
     for (int64_t rc = r0; rc < r1; rc += FIN_NT) {
         const int64_t r = rc + tid;
-        const bool f = r < r1 && alive[r] != 0;
+        const bool f = r < r1 && alive[r] > 0;
         const unsigned long long m = __ballot(f);
         if (lane == 0) s_w[wave] = __popcll(m);
         __syncthreads();
@@ -299,6 +295,23 @@ __global__ __launch_bounds__(FIN_NT) void k_fin_write(const int32_t* alive, int3
         if (f) nz_rows[base + woff + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)r;
         base += tot;
         __syncthreads();                           // s_w is rewritten next round
+    }
+}
+
+// Rows whose alive flag is -1 died in a layer that wrote the other ping-pong
+// buffer, so the output buffer still holds their older values: clear them (one
+// workgroup per row at a time, 16-byte stores; N is a multiple of 4 or the tail is
+// written by 4-byte stores).
+__global__ __launch_bounds__(256) void k_fin_zero(const int32_t* alive, int32_t rows, int32_t N, float* y_out) {
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+        if (alive[r] >= 0) continue;                 // uniform over the workgroup
+        float* y = y_out + (size_t)r * N;
+        if ((N & 3) == 0) {
+            float4* y4 = reinterpret_cast<float4*>(y);
+            for (int i = threadIdx.x; i < N / 4; i += 256) y4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+            for (int i = threadIdx.x; i < N; i += 256) y[i] = 0.f;
+        }
     }
 }
 
@@ -318,7 +331,7 @@ __device__ __forceinline__ LayerArgs chain_layer_args(const ChainArgs& c, int l,
     a.ycopy = (c.ckpt && (l + 1) % c.ckpt_every == 0 && l + 1 < L)
                   ? c.ckpt + (size_t)((l + 1) / c.ckpt_every - 1) * c.rows * N
                   : nullptr;
-    a.yzero = (c.compaction && !out_is_y) ? c.y_out : nullptr;
+    a.dead_mark = (c.compaction && !out_is_y) ? -1 : 0;
     a.idx = c.idx + l * NK;
     a.w = c.w + l * NK;
     a.b = c.b + (size_t)l * N;
@@ -528,15 +541,7 @@ __device__ __forceinline__ void run_layer_wide(const LayerArgs& a, int wg, int n
                         if ((alive >> t) & 1u) a.list_out[base++] = s_rows[t];
                 }
             }
-            if (a.alive && tid < nvalid) a.alive[s_rows[tid]] = (int32_t)((alive >> tid) & 1u);
-            if (a.yzero) {
-                for (int t = 0; t < nvalid; ++t) {
-                    if (!((alive >> t) & 1u)) {
-                        float* z = a.yzero + (size_t)s_rows[t] * N;
-                        for (int i = tid; i < N; i += NT) z[i] = 0.f;
-                    }
-                }
-            }
+            if (a.alive && tid < nvalid) a.alive[s_rows[tid]] = ((alive >> tid) & 1u) ? 1 : a.dead_mark;
         }
         __syncthreads();                           // s_rows, s_bits, s_last are reused
     }
@@ -1017,7 +1022,7 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
                 const int nv = min(T, R - tA * T);
                 const unsigned all = (full | (full >> 4) | (full >> 8) | (full >> 12)) & ((1u << nv) - 1u);
                 if (G > 1 && lane == 0) atomicExch(&a.tile_bits[tA], 0);
-                if (a.alive && lane < nv) a.alive[rowA] = (int32_t)((all >> lane) & 1u);
+                if (a.alive && lane < nv) a.alive[rowA] = ((all >> lane) & 1u) ? 1 : a.dead_mark;
                 if (a.list_out && all) {
                     baseB = lane == 0 ? atomicAdd(a.cnt_out, __popc(all)) : 0;
                     maskB = all;
@@ -1054,13 +1059,12 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
     int tile_p = -1, row_p = 0, orow_p = 0;          // the previous tile (outputs not yet stored)
     // Each wave stages its own outputs (its two blocks: neurons wbase .. wbase+127,
     // 4 rows) in a private 2 KB of LDS and stores them with 16-byte stores after the
-    // next barrier; no other wave touches that area.  `mine` = this part's row bits:
-    // where a row's slice of this part is all zero and dead rows must be cleared in
-    // another buffer (yzero), the slice's zeros go there too, so a row that dies is
-    // cleared by its parts without waiting for the other parts.
+    // next barrier; no other wave touches that area.  A row that dies is not cleared
+    // here: the other parts of its tile may still be reading it, and no kernel writes
+    // its own input (its alive flag says whether the finalize pass must clear it).
     const int wbase = p * SCHED_PART + 128 * wave;
     float* wout = L.out + 512 * wave;
-    auto store_own = [&](unsigned mine) {
+    auto store_own = [&]() {
         const int nv = min(T, R - tile_p * T);
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -1076,12 +1080,6 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
                 const float4 v = *reinterpret_cast<const float4*>(wout + e);
                 *reinterpret_cast<float4*>(a.yout + o) = v;
                 if (a.ycopy) *reinterpret_cast<float4*>(a.ycopy + o) = v;
-                if (!LINEAR && a.yzero && !((mine >> t) & 1u)) {
-                    // (a zero made here, so the compiler keeps no zero vector alive across the loop)
-                    float z;
-                    __asm__ volatile("v_mov_b32 %0, 0" : "=v"(z));
-                    *reinterpret_cast<float4*>(a.yzero + o) = make_float4(z, z, z, z);
-                }
             }
         }
     };
@@ -1115,9 +1113,9 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
         // (register moves of loop-carried row ids first, while nothing is outstanding)
         const int row_now = row_c, orow_now = orow_c;
         if (tile_p >= 0) {
-            const unsigned mine = (live || a.yzero) ? s_bits[(it + 2) % 3] : 0xfu;
+            const unsigned mine = live ? s_bits[(it + 2) % 3] : 0xfu;
             if (live && wave == 0) advance(tile_p, row_p, mine);   // before any store: nothing outstanding
-            store_own(mine);
+            store_own();
         }
         // the word of two tiles ago: read by every wave before this barrier, next
         // written after the next one
@@ -1152,7 +1150,7 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
             if (n1.j >= 0) wout[t * 128 + (n1.j - wbase)] = o1;
             bits |= ((o0 != 0.f && n0.j >= 0) || (o1 != 0.f && n1.j >= 0)) ? (1u << t) : 0u;
         }
-        if (live || (!LINEAR && a.yzero)) {
+        if (live) {
             // row bits of this part: its waves meet in LDS (read after the next barrier)
             unsigned wbits = 0u;                     // the wave's row bits, from one ballot per row
 #pragma unroll
@@ -1166,7 +1164,7 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
     // drain: the last tile's outputs and the rest of the liveness pipeline
     __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
     __syncthreads();
-    const unsigned mine_last = (live || a.yzero) ? s_bits[(it - 1) % 3] : 0xfu;
+    const unsigned mine_last = live ? s_bits[(it - 1) % 3] : 0xfu;
     if (live && wave == 0) {
         advance(tile_p, row_p, mine_last);
         __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
@@ -1174,7 +1172,7 @@ __device__ __forceinline__ void run_layer_sched(const LayerArgs& a, float* __res
         __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
         advance(-1, 0, 0u);
     }
-    store_own(mine_last);
+    store_own();
     __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
 }
 
@@ -1202,7 +1200,7 @@ __global__ __launch_bounds__(NT) void k_chain_sched(ChainArgs c) {
         a.ycopy = (c.ckpt && (l + 1) % c.ckpt_every == 0 && l + 1 < L)
                       ? c.ckpt + (size_t)((l + 1) / c.ckpt_every - 1) * c.rows * N
                       : nullptr;
-        a.yzero = (c.compaction && !out_is_y) ? c.y_out : nullptr;
+        a.dead_mark = (c.compaction && !out_is_y) ? -1 : 0;
         a.idx = c.idx + l * NK;
         a.w = c.w + l * NK;
         a.b = c.b + (size_t)l * N;

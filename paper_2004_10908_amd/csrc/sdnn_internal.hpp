@@ -19,7 +19,9 @@ struct LayerArgs {
     const float* yin;        // activations entering the layer
     float* yout;             // activations leaving it (same row ids)
     float* ycopy;            // optional second copy of the output rows (checkpoint), or null
-    float* yzero;            // rows found all-zero are also zeroed here (or null)
+    int32_t dead_mark;       // value written to alive[row] for a row found all-zero here: 0, or -1
+                             // where the final output buffer still holds the row's older values
+                             // (the finalize pass zeroes those rows; no layer writes its own input)
     const int32_t* idx;      // [N][K] this layer
     const float* w;          // [N][K]
     const float* b;          // [N]
@@ -165,7 +167,9 @@ __global__ void k_chain_init(int32_t* cnt, int32_t L, int32_t rows, int32_t comp
 constexpr int FIN_BLOCKS = 64;   // workgroups of the finalize passes (each a consecutive row range)
 __global__ void k_fin_count(const int32_t* alive, int32_t rows, int32_t* part);
 __global__ void k_fin_write(const int32_t* alive, int32_t rows, const int32_t* part, int32_t* nz_rows, int32_t* n_nz,
-                            const int32_t* cnt, int32_t n_regions, int32_t L, int32_t* layer_rows);
+                            const int32_t* cnt, int32_t n_regions, int32_t L, int32_t* layer_rows,
+                            const int32_t* err, int32_t* host_err);
+__global__ void k_fin_zero(const int32_t* alive, int32_t rows, int32_t N, float* y_out);
 __global__ void k_fill_f32(float* p, int64_t n, float v);
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v);
 __global__ void k_check_params(const int32_t* idx, const float* w, const float* b, int32_t N, int32_t L,

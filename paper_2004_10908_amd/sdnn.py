@@ -58,6 +58,7 @@ PROTOTYPES = [
     ("sdnn_mse", _I32, [_P, _P, _I64, _P, _P, _P]),
     ("sdnn_schedule_host", _I32, [_P, _I32, _I32, _I32, _P, _P, _P]),
     ("sdnn_check_device", _I32, [_P, _P]),
+    ("sdnn_inject_device_error", _I32, [_P, _I32, _P]),
     ("sdnn_destroy", None, [_P]),
     ("sdnn_last_error", ctypes.c_char_p, []),
     ("sdnn_version", ctypes.c_char_p, []),
@@ -207,6 +208,10 @@ def sdnn_check_device(h, stream=None) -> None:
     _chk(lib().sdnn_check_device(h, _stream(stream)), "sdnn_check_device")
 
 
+def sdnn_inject_device_error(h, code: int, stream=None) -> None:
+    _chk(lib().sdnn_inject_device_error(h, code, _stream(stream)), "sdnn_inject_device_error")
+
+
 def sdnn_destroy(h) -> None:
     lib().sdnn_destroy(h)
 
@@ -302,6 +307,9 @@ class Net:
 
     def check_device(self, stream=None) -> None:
         sdnn_check_device(self.h, stream)
+
+    def inject_device_error(self, code: int, stream=None) -> None:
+        sdnn_inject_device_error(self.h, code, stream)
 
     def close(self) -> None:
         if self.h is not None:

@@ -3,13 +3,19 @@ library's results with the oracle under the tie-aware protocol.
 
 Protocol (readings of the paper's unstated precision contract, written here as the
 checks that apply them):
-* layer-synchronized: feed the GPU's Y_l to the oracle's layer; every output must
-  satisfy |y_gpu - y_ref| <= max(1e-5 |y_ref|, gamma_33 S) and may differ in being
+* layer-synchronized, on the chain's own activations: a net created with
+  ckpt_every = 1 writes every Y_l of a forward into the checkpoint buffer; the
+  oracle's layer is fed the GPU's Y_l and every output of the GPU's Y_{l+1} must
+  satisfy |y_gpu - y_ref| <= max(1e-5 |y_ref|, gamma_33 S), and may differ in being
   zero / nonzero only where the oracle flags the output tie-ambiguous;
-* end-to-end: the set of nonzero final rows must be identical, and on those rows
-  |y_gpu - y_ref| <= 1e-5 max(|y_ref|, max_j |y_ref[r, :]|) (row-scaled);
-* gradients, per layer: ||d||_2 <= 1e-4 ||g_ref||_2 and elementwise
-  |d| <= max(1e-4 |g_ref|, gamma_R S_g) with S_g the sum of |summands|.
+* the liveness bookkeeping must agree with the values: the rows the library says
+  entered layer l+1 are exactly the rows of its Y_{l+1} with a nonzero;
+* end to end, the set of nonzero final rows must equal the oracle's (a forward of
+  the exact net from Y_0) except for rows in which the layer-synchronized pass saw
+  a tie-ambiguous zero / nonzero flip; rows reported dead are exactly zero;
+* gradients: per layer ||d||_2 <= 1e-4 ||g_ref||_2, with the oracle's backward
+  replayed on the GPU's own activations (so both sides use the same masks), and
+  layer-synchronized elementwise bounds in the one-layer tests.
 """
 from __future__ import annotations
 
@@ -51,7 +57,8 @@ def host_layers(idx, w, b, first=0, last=None):
 
 
 def check_layer_sync(y_in, y_gpu, layer, clamp):
-    """Layer-synchronized comparison; returns (max scaled error, flips)."""
+    """Layer-synchronized comparison of one layer; returns the ids of rows with a
+    (tie-ambiguous) zero / nonzero flip."""
     idx, w, b = layer
     ref, _, z, s = oracle.layer_forward(idx, w, b, clamp, y_in, want_zs=True)
     y = np.asarray(y_gpu, np.float64)
@@ -61,74 +68,69 @@ def check_layer_sync(y_in, y_gpu, layer, clamp):
     assert not (flip & ~amb).any(), f"zero/nonzero disagreement at a non-ambiguous output: {np.argwhere(flip & ~amb)[:5]}"
     bad = (np.abs(y - ref) > tol) & ~amb
     assert not bad.any(), f"{int(bad.sum())} outputs outside tolerance, worst {np.abs(y - ref)[bad].max()}"
-    return int(flip.sum())
+    return set(np.flatnonzero(flip.any(axis=1)).tolist())
 
 
-def check_end_to_end(y_gpu, nz_gpu, ref):
-    """End-to-end comparison against an oracle ForwardResult.
+def forward_layers(net, y0, batch_off=None, mode="graph"):
+    """Forward of a net created with ckpt_every = 1 into a zero-filled checkpoint
+    buffer.  Returns (outputs, nonzero row ids, [Y_0 .. Y_L] as host float32):
+    rows that left the work list before layer l read zero in Y_l."""
+    assert net.ckpt_every == 1, "needs a net with ckpt_every = 1"
+    rows = y0.shape[0]
+    dev = y0.device
+    o = {"y": torch.full((rows, net.n_neurons), float("nan"), dtype=torch.float32, device=dev),
+         "nz_rows": torch.empty(max(rows, 1), dtype=torch.int32, device=dev),
+         "n_nz": torch.empty(1, dtype=torch.int32, device=dev),
+         "ckpt": torch.zeros(max(net.ckpt_numel(rows), 1), dtype=torch.float32, device=dev),
+         "layer_rows": torch.empty(net.n_layers + 1, dtype=torch.int32, device=dev)}
+    net.set_exec(mode)
+    net.forward(y0, batch_off=batch_off, out=o)
+    torch.cuda.synchronize()
+    n = int(o["n_nz"].item())
+    nz = o["nz_rows"][:n].cpu().numpy()
+    L = net.n_layers
+    ck = o["ckpt"][: (L - 1) * rows * net.n_neurons].view(max(L - 1, 0), rows, net.n_neurons) if L > 1 else None
+    ys = [y0.cpu().numpy()] + [ck[l].cpu().numpy() for l in range(L - 1)] + [o["y"].cpu().numpy()]
+    return o, nz, ys
 
-    With ``ref.bound`` (the propagated fp32 error bound) an output may differ from
-    the oracle by max(1e-5 * row scale, bound), and a row may be alive on one side
-    only if all its outputs are within the bound of the oracle's.  Without it the
-    plain row-scaled 1e-5 check applies and the row sets must match exactly.
-    """
-    nz_ref = ref.nz_rows
+
+def check_chain(layers, clamp, ys, layer_rows, nz_gpu, y0h, compact=True):
+    """Every layer of one GPU forward, layer-synchronized; liveness counts against the
+    values; the final row set against the oracle's.  Returns the number of
+    tie-ambiguous flips seen."""
+    L = len(layers)
+    assert len(ys) == L + 1
+    tie_rows = set()
+    prof = np.asarray(layer_rows)
+    assert prof[0] == ys[0].shape[0]
+    for l in range(L):
+        tie_rows |= check_layer_sync(ys[l], ys[l + 1], layers[l], clamp)
+        alive = int((ys[l + 1] != 0).any(axis=1).sum())
+        if compact and l + 1 < L:
+            assert prof[l + 1] == alive, f"layer {l + 1}: work list of {prof[l + 1]} rows, {alive} alive rows"
+    nz_gpu = np.asarray(nz_gpu)
+    assert (np.diff(nz_gpu) > 0).all(), "nonzero-row ids must be ascending"
+    assert prof[L] == len(nz_gpu)
+    assert np.array_equal(nz_gpu, np.flatnonzero((ys[L] != 0).any(axis=1))), "nz_rows disagree with the output"
+    ref = oracle.forward(layers, y0h, clamp)
+    diff = np.setxor1d(nz_gpu, ref.nz_rows)
+    assert set(diff.tolist()) <= tie_rows, f"rows {diff[:5]} differ from the oracle's set without a tie flip"
+    return len(tie_rows)
+
+
+def check_end_to_end(y_gpu, nz_gpu, ref, tie_rows=()):
+    """Row set of a forward against an oracle ForwardResult (exact, except rows with
+    a tie flip found by a layer-synchronized pass); rows reported dead are zero.
+    Values are checked layer by layer (check_chain), not here: each layer of the
+    challenge nets has gain sum |w| = 2, so rounding of any fp32 evaluation grows
+    with depth on rows that never saturate."""
     y = np.asarray(y_gpu, np.float64)
     nz_gpu = np.asarray(nz_gpu)
     assert (np.diff(nz_gpu) > 0).all(), "nonzero-row ids must be ascending"
-    scale = np.maximum(np.abs(ref.y), np.abs(ref.y).max(axis=1, keepdims=True))
-    tol = 1e-5 * scale if ref.bound is None else np.maximum(1e-5 * scale, ref.bound)
-    err = np.abs(y - ref.y)
-    if ref.bound is None:
-        assert np.array_equal(nz_gpu, nz_ref), "nonzero-row sets differ"
-    else:
-        diff = np.setxor1d(nz_gpu, nz_ref)
-        assert (err[diff] <= ref.bound[diff]).all(), f"rows {diff[:5]} differ in liveness beyond the bound"
+    diff = np.setxor1d(nz_gpu, ref.nz_rows)
+    assert set(diff.tolist()) <= set(tie_rows), f"nonzero-row sets differ at rows {diff[:5]}"
     gpu_dead = np.setdiff1d(np.arange(y.shape[0]), nz_gpu)
     assert (y[gpu_dead] == 0).all(), "rows reported dead must be exactly zero"
-    bad = err > tol
-    assert not bad.any(), f"{int(bad.sum())} outputs outside tolerance; worst excess {(err - tol)[bad].max()}"
-
-
-def check_grad(g_gpu, g_ref, bound, what, normwise=True):
-    """|g - g_ref| <= max(1e-4 |g_ref|, bound) elementwise, and (optionally) the
-    normwise 1e-4 check, which only holds where the chain is well conditioned."""
-    g = np.asarray(g_gpu, np.float64)
-    d = g - g_ref
-    if normwise:
-        nref = np.linalg.norm(g_ref)
-        assert np.linalg.norm(d) <= 1e-4 * nref + 1e-30, f"{what}: normwise {np.linalg.norm(d)} vs {nref}"
-    tol = np.maximum(1e-4 * np.abs(g_ref), bound)
-    bad = np.abs(d) > tol
-    assert not bad.any(), f"{what}: {int(bad.sum())} elements outside tolerance, worst excess {(np.abs(d) - tol)[bad].max()}"
-
-
-def backward_bounds(layers, ys, eys, dy_last, clamp, rows_groups=256):
-    """First-order error bounds of an fp32 backward pass (masks taken as the oracle's).
-
-    ys/eys: exact activations and their forward error bounds per layer; dy_last is
-    the (exact, shared) dL/dY_L.  Uses the oracle's layer backward on magnitudes:
-    for dW the rounded terms are (|G| + E_G)(|Y| + E_Y), for dY they are |w|(|G| + E_G).
-    Returns per-layer (dW ref, E_dW, db ref, E_db) and (dY_0 ref, E_dY0).
-    """
-    L = len(layers)
-    R = ys[0].shape[0]
-    gR = oracle.gamma(R + rows_groups)
-    D = np.asarray(dy_last, np.float64)
-    ED = np.zeros_like(D)
-    out = [None] * L
-    for l in range(L - 1, -1, -1):
-        idx, w, _ = layers[l]
-        aw = np.abs(w)
-        Y, EY, Yo = ys[l], eys[l], ys[l + 1]
-        dw, db, dyi = oracle.layer_backward(idx, w, clamp, Y, Yo, D)
-        dwA, dbA, dyA = oracle.layer_backward(idx, aw, clamp, np.abs(Y) + EY, Yo, np.abs(D) + ED)
-        dwB, dbB, dyB = oracle.layer_backward(idx, aw, clamp, np.abs(Y), Yo, np.abs(D))
-        gK = oracle.gamma(int(np.bincount(idx.ravel(), minlength=idx.shape[0]).max()) + 1)
-        out[l] = (dw, (dwA - dwB) + gR * dwA, db, (dbA - dbB) + gR * dbA)
-        ED = (dyA - dyB) + gK * dyA
-        D = dyi
-    return out, D, ED
 
 
 def run_forward(net, y0, batch_off=None, mode="auto", ckpt=False):
@@ -137,3 +139,12 @@ def run_forward(net, y0, batch_off=None, mode="auto", ckpt=False):
     torch.cuda.synchronize()
     n = int(o["n_nz"].item())
     return o, o["nz_rows"][:n].cpu().numpy()
+
+
+def normwise(g_gpu, g_ref, what, tol=1e-4):
+    """||g - g_ref||_2 <= tol ||g_ref||_2; returns the ratio."""
+    g = np.asarray(g_gpu, np.float64)
+    d = np.linalg.norm(g - g_ref)
+    n = np.linalg.norm(g_ref)
+    assert d <= tol * n + 1e-30, f"{what}: normwise error {d} vs {tol} x {n}"
+    return d / n if n > 0 else 0.0

@@ -5,7 +5,8 @@ import torch
 
 import oracle
 import sdnn_inputs as gen
-from tests.sdnn_gpu import DEV, check_end_to_end, check_layer_sync, host_layers, run_forward, upload
+from tests.sdnn_gpu import (DEV, check_chain, check_end_to_end, check_layer_sync, forward_layers, host_layers,
+                            run_forward, upload)
 
 pytestmark = pytest.mark.gpu
 
@@ -45,20 +46,17 @@ def test_layer_sync_small_nets(P, N, rows, weight, bias, clamp):
 def test_c1_all_modes_match_oracle_and_each_other(P):
     cfg = gen.CONFIGS["C1"]
     idx, w, b = upload(cfg)
+    lay = host_layers(idx, w, b)
     y0h = gen.make_inputs(cfg)
-    ref = oracle.forward(host_layers(idx, w, b), y0h, cfg.clamp, bound=True)
     y0 = torch.from_numpy(y0h).to(DEV)
     outs = {}
     for flags in (0, P.sdnn.SDNN_NO_COMPACTION):
-        net = _net(P, idx, w, b, cfg.rows, flags=flags)
+        net = _net(P, idx, w, b, cfg.rows, flags=flags, ckpt_every=1)
         for m in MODES:
-            o, nz = run_forward(net, y0, mode=m)
-            check_end_to_end(o["y"].cpu().numpy(), nz, ref)
-            prof = o["layer_rows"].cpu().numpy()
-            assert prof[0] == cfg.rows and prof[-1] == len(nz)
-            if flags == 0:
-                assert list(prof[1:cfg.n_layers + 1]) == ref.alive_after, (m, prof[:5], ref.alive_after[:5])
+            o, nz, ys = forward_layers(net, y0, mode=m)
+            check_chain(lay, cfg.clamp, ys, o["layer_rows"].cpu().numpy(), nz, y0h, compact=flags == 0)
             outs[(flags, m)] = o["y"].clone()
+        net.close()
     base = outs[(0, "graph")]
     for k, v in outs.items():
         assert torch.equal(v, base), k
@@ -68,36 +66,71 @@ def test_sustained_companion_small(P):
     """Row densities U(0.1, 0.5) keep rows alive through every layer."""
     cfg = gen.CONFIGS["S2"].with_(n_neurons=1024, n_layers=40, rows=333)
     idx, w, b = upload(cfg)
+    lay = host_layers(idx, w, b)
     y0h = gen.make_inputs(cfg)
-    ref = oracle.forward(host_layers(idx, w, b), y0h, cfg.clamp, bound=True)
-    assert ref.alive.sum() > 50
-    net = _net(P, idx, w, b, cfg.rows)
+    net = _net(P, idx, w, b, cfg.rows, ckpt_every=1)
     y0 = torch.from_numpy(y0h).to(DEV)
     for m in ("graph", "persistent"):
-        o, nz = run_forward(net, y0, mode=m)
-        check_end_to_end(o["y"].cpu().numpy(), nz, ref)
-        assert list(o["layer_rows"].cpu().numpy()[1:cfg.n_layers + 1]) == ref.alive_after
+        o, nz, ys = forward_layers(net, y0, mode=m)
+        assert len(nz) > 50
+        check_chain(lay, cfg.clamp, ys, o["layer_rows"].cpu().numpy(), nz, y0h)
 
 
 def test_batched_forms_equal_plain(P):
     cfg = gen.CONFIGS["S2"].with_(n_neurons=2048, n_layers=24, rows=1500)
     idx, w, b = upload(cfg)
+    lay = host_layers(idx, w, b)
     y0h = gen.make_inputs(cfg)
     y0 = torch.from_numpy(y0h).to(DEV)
-    ref = oracle.forward(host_layers(idx, w, b), y0h, cfg.clamp, bound=True)
     off = [0, 0, 311, 312, 900, 900, 1499, 1500]        # uneven, with empty and 1-row batches
-    net = _net(P, idx, w, b, cfg.rows)
+    net = _net(P, idx, w, b, cfg.rows, ckpt_every=1)
     base = None
     for m in MODES:
-        o, nz = run_forward(net, y0, batch_off=off, mode=m)
-        check_end_to_end(o["y"].cpu().numpy(), nz, ref)
-        prof = o["layer_rows"].cpu().numpy()
-        assert list(prof[1:cfg.n_layers + 1]) == ref.alive_after
+        o, nz, ys = forward_layers(net, y0, batch_off=off, mode=m)
         if base is None:
+            check_chain(lay, cfg.clamp, ys, o["layer_rows"].cpu().numpy(), nz, y0h)
             base = o["y"].clone()
+            base_ys = ys
         assert torch.equal(o["y"], base), m
+        assert all(np.array_equal(a, c) for a, c in zip(ys, base_ys)), m
     o, nz = run_forward(net, y0, batch_off=None, mode="graph")
     assert torch.equal(o["y"], base)
+
+
+# Multi-tile pipelines: every one of the scheduled kernel's 256 / G tile streams runs
+# several 4-row tiles (next-tile copies, buffer toggle, the deferred liveness words,
+# the lockstep), checked element by element on every layer through the chain's own
+# activations.  He weights with a negative bias make rows die at different layers with
+# mixed-sign sums (a row alive overall can have an all-zero slice of one part).
+@pytest.mark.parametrize("N,rows,layers,weight,bias", [
+    (1024, 4000, 10, "he", -0.05),       # G = 1: 256 streams, ~4 tiles each
+    (2048, 2600, 10, "he", -0.05),       # G = 2: 128 streams, ~5 tiles each
+    (4096, 4000, 16, "he", -0.05),       # G = 4: 64 streams, ~16 tiles each
+    (4096, 3000, 24, "const", -0.35),    # the C2 net with per-row densities (S2), rows saturate at 32
+])
+def test_chain_layer_sync_multi_tile(P, N, rows, layers, weight, bias):
+    if weight == "const":
+        cfg = gen.CONFIGS["S2"].with_(n_neurons=N, n_layers=layers, rows=rows, seed=N + rows)
+    else:
+        cfg = gen.tiny_config(N, layers, rows, seed=N + rows, weight=weight, bias=bias, row_density=True)
+    idx, w, b = upload(cfg)
+    lay = host_layers(idx, w, b)
+    y0h = gen.make_inputs(cfg)
+    y0 = torch.from_numpy(y0h).to(DEV)
+    net = _net(P, idx, w, b, rows, ckpt_every=1)
+    assert net.plan["variant"] == 2, net.plan
+    base = None
+    for m in ("persistent", "graph"):
+        o, nz, ys = forward_layers(net, y0, mode=m)
+        prof = o["layer_rows"].cpu().numpy()
+        if base is None:
+            ties = check_chain(lay, cfg.clamp, ys, prof, nz, y0h)
+            print(f"N={N} rows={rows}: alive per layer {prof.tolist()}, tie-flip rows {ties}")
+            assert prof[layers // 2] > 0          # rows still alive half-way: the deep layers are exercised
+            base = ys
+        else:
+            assert all(np.array_equal(a, c) for a, c in zip(ys, base)), m
+    net.close()
 
 
 def test_positive_bias_turns_compaction_off_and_matches(P):
@@ -106,26 +139,24 @@ def test_positive_bias_turns_compaction_off_and_matches(P):
     b[2, 5] = 0.5
     y0h = gen.make_inputs(cfg)
     y0h[3] = 0.0
-    ref = oracle.forward(host_layers(idx, w, b), y0h, cfg.clamp, bound=True)
-    net = _net(P, idx, w, b, cfg.rows)
-    o, nz = run_forward(net, torch.from_numpy(y0h).to(DEV), mode="graph")
-    check_end_to_end(o["y"].cpu().numpy(), nz, ref)
+    net = _net(P, idx, w, b, cfg.rows, ckpt_every=1)
+    o, nz, ys = forward_layers(net, torch.from_numpy(y0h).to(DEV), mode="graph")
+    check_chain(host_layers(idx, w, b), cfg.clamp, ys, o["layer_rows"].cpu().numpy(), nz, y0h, compact=False)
     assert (o["layer_rows"].cpu().numpy()[:cfg.n_layers] == cfg.rows).all()   # no compaction
 
 
 def test_empty_and_single_row_calls(P):
     cfg = gen.tiny_config(128, 3, 5, seed=9, weight="he", bias=-0.01)
     idx, w, b = upload(cfg)
-    net = _net(P, idx, w, b, 5)
+    net = _net(P, idx, w, b, 5, ckpt_every=1)
     y0 = torch.zeros(0, 128, device=DEV)
     o = net.forward(y0, profile=True)
     torch.cuda.synchronize()
     assert int(o["n_nz"].item()) == 0 and (o["layer_rows"].cpu().numpy() == 0).all()
     y1h = gen.make_inputs(cfg.with_(rows=1))
-    ref = oracle.forward(host_layers(idx, w, b), y1h, cfg.clamp, bound=True)
     for m in MODES:
-        o, nz = run_forward(net, torch.from_numpy(y1h).to(DEV), mode=m)
-        check_end_to_end(o["y"].cpu().numpy(), nz, ref)
+        o, nz, ys = forward_layers(net, torch.from_numpy(y1h).to(DEV), mode=m)
+        check_chain(host_layers(idx, w, b), cfg.clamp, ys, o["layer_rows"].cpu().numpy(), nz, y1h)
 
 
 def test_argument_errors(P):
@@ -273,4 +304,36 @@ def test_kernel_timing_api(P):
     net.forward(y0, out=o)
     torch.cuda.synchronize()
     assert net.kernel_time()[1] == 0
+    net.close()
+
+
+@pytest.mark.parametrize("N,rows", [(1024, 600), (65536, 40)])
+def test_device_error_is_reported_by_the_next_call(P, N, rows):
+    """An error word raised on the device (injected from the host here, as a timed-out
+    barrier would raise it): every grid barrier of the persistent chain gives up, the
+    kernels return normally, the finalize pass publishes the word, and the next call
+    returns SDNN_EDEVICE without launching anything; a recreated net works."""
+    cfg = gen.CONFIGS["S2"].with_(n_neurons=N, n_layers=6, rows=rows, seed=5)
+    idx, w, b = upload(cfg)
+    y0 = torch.from_numpy(gen.make_inputs(cfg)).to(DEV)
+    net = _net(P, idx, w, b, rows)
+    ref, _ = run_forward(net, y0, mode="persistent")
+    ref_y = ref["y"].clone()
+    net.check_device()
+    net.inject_device_error(1)
+    o = net.forward(y0, out=ref)                  # runs; every barrier gives up
+    torch.cuda.synchronize()
+    with pytest.raises(P.SdnnError, match="EDEVICE"):
+        net.forward(y0, out=ref)
+    with pytest.raises(P.SdnnError, match="EDEVICE"):
+        net.layer(0, y0)
+    with pytest.raises(P.SdnnError, match="EDEVICE"):
+        net.check_device()
+    with pytest.raises(P.SdnnError, match="EINVAL"):
+        net.inject_device_error(0)
+    net.close()
+    net = _net(P, idx, w, b, rows)
+    o, _ = run_forward(net, y0, mode="persistent")
+    net.check_device()
+    assert torch.equal(o["y"], ref_y)
     net.close()

@@ -7,7 +7,7 @@ import torch
 
 import oracle
 import sdnn_inputs as gen
-from tests.sdnn_gpu import DEV, check_end_to_end, host_layers, upload
+from tests.sdnn_gpu import DEV, check_end_to_end, check_layer_sync, host_layers, upload
 
 pytestmark = pytest.mark.gpu
 
@@ -27,14 +27,20 @@ def test_streamed_equals_resident(P, N, layers, rows, slots):
     idx, w, b = upload(cfg)
     y0h = gen.make_inputs(cfg)
     y0 = torch.from_numpy(y0h).to(DEV)
-    ref = oracle.forward(host_layers(idx, w, b), y0h, cfg.clamp, bound=True)
-    # resident parameters, same kernel family, layer by layer over all rows
+    lay = host_layers(idx, w, b)
+    # resident parameters, same kernel family, layer by layer over all rows, each layer
+    # checked against the oracle fed the same inputs
     net = P.Net(idx, w, b, max_rows=rows, flags=P.sdnn.SDNN_NO_SCHEDULE | P.sdnn.SDNN_NO_COMPACTION)
     assert net.plan["variant"] != 2
     y = y0
+    ties = set()
     for l in range(layers):
-        y = net.layer(l, y)
+        yn = net.layer(l, y)
+        torch.cuda.synchronize()
+        ties |= check_layer_sync(y.cpu().numpy(), yn.cpu().numpy(), lay[l], cfg.clamp)
+        y = yn
     base = y.clone()
+    ref = oracle.forward(lay, y0h, cfg.clamp)
     net.close()
     sf = StreamedForward(idx.cpu().pin_memory(), w.cpu().pin_memory(), b.cpu().pin_memory(), rows, slots=slots)
     out = torch.full_like(y0, float("nan"))
@@ -44,7 +50,7 @@ def test_streamed_equals_resident(P, N, layers, rows, slots):
         torch.cuda.synchronize()
         assert torch.equal(out, base), rep
     nz = torch.nonzero((out != 0).any(dim=1)).flatten().cpu().numpy().astype(np.int32)
-    check_end_to_end(out.cpu().numpy(), nz, ref)
+    check_end_to_end(out.cpu().numpy(), nz, ref, ties)
     sf.close()
 
 

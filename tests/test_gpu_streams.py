@@ -6,7 +6,7 @@ import torch
 
 import oracle
 import sdnn_inputs as gen
-from tests.sdnn_gpu import DEV, check_end_to_end, host_layers, run_forward, upload
+from tests.sdnn_gpu import DEV, check_chain, forward_layers, host_layers, run_forward, upload
 
 pytestmark = pytest.mark.gpu
 
@@ -27,12 +27,11 @@ def test_streams_equal_single_stream(P, N, layers, rows):
     idx, w, b = upload(cfg)
     y0h = gen.make_inputs(cfg)
     y0 = torch.from_numpy(y0h).to(DEV)
-    ref = oracle.forward(host_layers(idx, w, b), y0h, cfg.clamp, bound=True)
     off = [0, 150, 151, 151, 480, 700 if rows > 700 else rows - 1, rows - 1, rows]   # uneven, empty, 1-row
     off = sorted(min(v, rows) for v in off)
-    net = P.Net(idx, w, b, max_rows=rows)
-    o, nz = run_forward(net, y0, batch_off=off, mode="graph")
-    check_end_to_end(o["y"].cpu().numpy(), nz, ref)
+    net = P.Net(idx, w, b, max_rows=rows, ckpt_every=1)
+    o, nz, ys = forward_layers(net, y0, batch_off=off, mode="graph")
+    check_chain(host_layers(idx, w, b), cfg.clamp, ys, o["layer_rows"].cpu().numpy(), nz, y0h)
     base = o["y"].clone()
     net.close()
     for k in (1, 2, 3):

@@ -8,7 +8,7 @@ import torch
 
 import oracle
 import sdnn_inputs as gen
-from tests.sdnn_gpu import DEV, check_end_to_end, check_layer_sync, host_layers, run_forward, upload
+from tests.sdnn_gpu import DEV, check_chain, check_layer_sync, forward_layers, host_layers, run_forward, upload
 
 pytestmark = pytest.mark.gpu
 
@@ -31,10 +31,10 @@ def P():
 def test_wide_forward_matches_oracle(P, N, layers, rows):
     cfg = gen.CONFIGS["S2"].with_(n_neurons=N, n_layers=layers, rows=rows, seed=N + rows)
     idx, w, b = upload(cfg)
+    lay = host_layers(idx, w, b)
     y0h = gen.make_inputs(cfg)
-    ref = oracle.forward(host_layers(idx, w, b), y0h, cfg.clamp, bound=True)
     y0 = torch.from_numpy(y0h).to(DEV)
-    net = P.Net(idx, w, b, max_rows=rows)
+    net = P.Net(idx, w, b, max_rows=rows, ckpt_every=1)
     if 2 * N * 4 > 160 * 1024:
         assert net.plan["variant"] == 3, net.plan    # not even 2 LDS rows fit: the wide kernel is the default
     else:
@@ -42,14 +42,39 @@ def test_wide_forward_matches_oracle(P, N, layers, rows):
         net.set_plan(32, 1024, 3)
     base = None
     for m in MODES:
-        o, nz = run_forward(net, y0, mode=m)
-        check_end_to_end(o["y"].cpu().numpy(), nz, ref)
-        prof = o["layer_rows"].cpu().numpy()
-        assert list(prof[1:layers + 1]) == ref.alive_after, (m, prof)
+        o, nz, ys = forward_layers(net, y0, mode=m)
         if base is None:
+            check_chain(lay, cfg.clamp, ys, o["layer_rows"].cpu().numpy(), nz, y0h)
             base = o["y"].clone()
         else:
             assert torch.equal(o["y"], base), m
+    net.close()
+
+
+# Several tiles per workgroup (grid-stride LDS kernel at 16384 neurons) and per XCD
+# tile stream (wide kernel at 65536 neurons), every layer of the chain checked
+# element by element through its own activations.
+@pytest.mark.parametrize("N,layers,rows,plan", [(16384, 8, 2400, None), (16384, 6, 2400, (32, 1024, 3)),
+                                                (65536, 6, 1200, None)])
+def test_wide_chain_layer_sync_multi_tile(P, N, layers, rows, plan):
+    cfg = gen.CONFIGS["S3"].with_(n_neurons=N, n_layers=layers, rows=rows, seed=N + rows + layers)
+    idx, w, b = upload(cfg)
+    lay = host_layers(idx, w, b)
+    y0h = gen.make_inputs(cfg)
+    y0 = torch.from_numpy(y0h).to(DEV)
+    net = P.Net(idx, w, b, max_rows=rows, ckpt_every=1)
+    if plan is not None:
+        net.set_plan(*plan)
+    base = None
+    for m in ("persistent", "graph_merged"):
+        o, nz, ys = forward_layers(net, y0, batch_off=[0, rows // 3, rows // 3 + 1, rows], mode=m)
+        if base is None:
+            prof = o["layer_rows"].cpu().numpy()
+            check_chain(lay, cfg.clamp, ys, prof, nz, y0h)
+            assert prof[layers - 1] > 0, prof
+            base = ys
+        else:
+            assert all(np.array_equal(a, c) for a, c in zip(ys, base)), m
     net.close()
 
 
@@ -60,18 +85,17 @@ def test_wide_variants_bitwise_equal(P):
     cfg = gen.CONFIGS["S2"].with_(n_neurons=N, n_layers=layers, rows=rows, seed=91)
     idx, w, b = upload(cfg)
     y0h = gen.make_inputs(cfg)
-    ref = oracle.forward(host_layers(idx, w, b), y0h, cfg.clamp, bound=True)
     y0 = torch.from_numpy(y0h).to(DEV)
     off = [0, 40, 40, 41, 200, rows]
-    net = P.Net(idx, w, b, max_rows=rows)
+    net = P.Net(idx, w, b, max_rows=rows, ckpt_every=1)
     base = None
     for T, NT, v in [(4, 512, 0)] + WIDE:
         plan = net.set_plan(T, NT, v)
         assert (plan["rows_per_tile"], plan["threads"], plan["variant"]) == (T, NT, v)
         for m in ("graph", "persistent"):
-            o, nz = run_forward(net, y0, batch_off=off, mode=m)
+            o, nz, ys = forward_layers(net, y0, batch_off=off, mode=m)
             if base is None:
-                check_end_to_end(o["y"].cpu().numpy(), nz, ref)
+                check_chain(host_layers(idx, w, b), cfg.clamp, ys, o["layer_rows"].cpu().numpy(), nz, y0h)
                 base = (o["y"].clone(), list(nz))
             else:
                 assert torch.equal(o["y"], base[0]), (T, NT, v, m)
@@ -97,10 +121,12 @@ def test_wide_layer_sync_clamp_and_positive_bias(P, T, NT, v):
         torch.cuda.synchronize()
         check_layer_sync(y.cpu().numpy(), yn.cpu().numpy(), lay[l], clamp)
         y = yn
-    ref = oracle.forward(lay, y0h, clamp, bound=True)
+    net.close()
+    net = P.Net(idx, w, b, max_rows=rows, clamp=clamp, ckpt_every=1)
+    net.set_plan(T, NT, v)
     for m in MODES:
-        o, nz = run_forward(net, torch.from_numpy(y0h).to(DEV), mode=m)
-        check_end_to_end(o["y"].cpu().numpy(), nz, ref)
+        o, nz, ys = forward_layers(net, torch.from_numpy(y0h).to(DEV), mode=m)
+        check_chain(lay, clamp, ys, o["layer_rows"].cpu().numpy(), nz, y0h, compact=False)
     net.close()
 
 

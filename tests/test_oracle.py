@@ -345,3 +345,57 @@ def test_fixed_relative_tolerance_is_unreachable_in_fp32_for_unsaturated_rows(or
     assert (np.abs(y32 - ref.y) > 1e-5 * scale).any()
     assert (np.abs(y32 - ref.y) <= np.maximum(1e-5 * scale, ref.bound)).all()
     assert all(w.sum(axis=1).max() == 2.0 for _, w, _ in layers)
+
+
+def _crafted_neuron(bias: float):
+    """One neuron of 32 inputs all equal to 1: slot 0 weight 1, slots 1..31 weight 2^-24.
+    Summed in slot order in fp32, every 1 + 2^-24 is a tie that rounds back to 1 (to
+    even), so the fp32 sum loses 31 u (u = 2^-24) against the exact 1 + 31 u: the
+    summation-error bound gamma_33 S is reached to within 33 / 31."""
+    N, K = 32, 32
+    idx = np.tile(np.arange(K, dtype=np.int32), (N, 1))
+    w = np.full((N, K), 2.0 ** -24, np.float32)
+    w[:, 0] = 1.0
+    b = np.full(N, bias, np.float32)
+    y = np.ones((1, N), np.float32)
+    acc = np.float32(0.0)
+    for k in range(K):
+        acc = np.float32(acc + np.float32(w[0, k] * y[0, idx[0, k]]))
+    z32 = np.float32(acc + b[0])
+    return (idx, w, b), y, float(z32)
+
+
+def test_tie_margin_and_layer_bound_are_tight(orc):
+    """The fp32 rounding margin gamma_33 S used by the tie flags, the layer-synchronized
+    tolerance and the one-layer error bound is not loose: on a crafted neuron a plain
+    fp32 evaluation in slot order comes within a small factor of it, so a margin 2x or
+    10x too wide (or a gamma with too many terms) fails here, while fp32 results never
+    leave it (the other pins)."""
+    U = 2.0 ** -24
+    # no bias: the rounding error of the sum reaches 31 u against the bound gamma_33 (1 + 31 u)
+    layer, y, z32 = _crafted_neuron(0.0)
+    ref, _, z, s = orc.layer_forward(*layer, 32.0, y, want_zs=True)
+    err = abs(z32 - z[0, 0])
+    assert err == 31 * U
+    bound = orc.layer_bound(*layer, y)[0, 0]
+    assert err <= bound <= 1.07 * err
+    assert orc.gamma(33) * s[0, 0] == bound
+    # bias -1 cancels the sum: the exact output 31 u is positive, the fp32 one is 0, a flip
+    # the tie flag must cover with a margin within 2.2x of |z| (S counts the bias too)
+    layer, y, z32 = _crafted_neuron(-1.0)
+    ref, _, z, s = orc.layer_forward(*layer, 32.0, y, want_zs=True)
+    assert z32 == 0.0 and z[0, 0] == 31 * U and ref[0, 0] > 0
+    amb = orc.ambiguous(z, s, 32.0)
+    assert amb[0, 0]
+    assert orc.gamma(33) * s[0, 0] <= 2.2 * abs(z[0, 0])
+    # the clamp side: c = 1 + 16 u, exact z = 1 + 31 u clamps to c, the fp32 sum 1 does not
+    layer, y, z32 = _crafted_neuron(0.0)
+    c = float(np.float32(1.0 + 16 * U))
+    ref, _, z, s = orc.layer_forward(*layer, c, y, want_zs=True)
+    assert ref[0, 0] == c and z32 < c
+    assert orc.ambiguous(z, s, c)[0, 0]
+    assert orc.gamma(33) * s[0, 0] <= 2.3 * abs(z[0, 0] - c)
+    # far from both kinks nothing is flagged
+    layer, y, _ = _crafted_neuron(-0.5)
+    _, _, z, s = orc.layer_forward(*layer, 32.0, y, want_zs=True)
+    assert not orc.ambiguous(z, s, 32.0).any()
