@@ -215,6 +215,23 @@ sdnn_status sdnn_layer_backward(sdnn_net net, int32_t layer, const float *y_in, 
 sdnn_status sdnn_mse(const float *y, const float *t, int64_t n, float *dy, float *loss, void *stream);
 
 /*
+ * sdnn_mse for callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same result,
+ * bitwise, with no scratch tail on `loss` and no allocation of any kind.
+ *   y, t     dev fp32 [n]
+ *   dy       dev fp32 [n] or NULL: 2 (y - t) / n
+ *   loss     dev fp32 [1] or NULL: sum (y - t)^2 / n
+ * The 256 per-workgroup partial sums live in a static device array of 1 KiB per
+ * GPU (held until the process ends); that holds them for every n >= 0, so no size
+ * is too large (n < 0 is SDNN_EINVAL).  Every call on one GPU shares that array:
+ * calls that overlap on one GPU (other streams, other threads) race and must be
+ * serialized by the caller.  The first call on a device looks up the array's
+ * device address (SDNN_EHIP if that fails; device ordinals >= 64 are
+ * SDNN_EUNSUPPORTED).
+ */
+sdnn_status sdnn_mse_noalloc(const float *y, const float *t, int64_t n, float *dy, float *loss, void *stream);
+
+/*
  * Host-side slot schedule of the resident-weight forward kernel, as sdnn_create
  * builds it (no GPU involved).  For each block of 64 neurons the neurons are
  * spread over the four 16-lane LDS service units of a wave and each lane's 32

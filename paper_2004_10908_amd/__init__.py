@@ -8,9 +8,9 @@ are hand-written HIP in ``csrc/`` behind the C ABI of ``include/sdnn.h``;
 """
 from .sdnn import (Net, SdnnError, lib, mse, sdnn_backward, sdnn_check_device, sdnn_ckpt_size, sdnn_create,
                    sdnn_inject_device_error,
-                   sdnn_destroy, sdnn_forward, sdnn_get_plan, sdnn_set_plan, sdnn_layer, sdnn_layer_backward, sdnn_mse, sdnn_schedule_host, sdnn_set_exec, sdnn_tune, sdnn_set_timing, sdnn_kernel_time,
+                   sdnn_destroy, sdnn_forward, sdnn_get_plan, sdnn_set_plan, sdnn_layer, sdnn_layer_backward, sdnn_mse, sdnn_mse_noalloc, sdnn_schedule_host, sdnn_set_exec, sdnn_tune, sdnn_set_timing, sdnn_kernel_time,
                    sdnn_version, sdnn_workspace_size, make_desc, LIB_PATH)
 
 __all__ = ["Net", "SdnnError", "lib", "mse", "sdnn_backward", "sdnn_check_device", "sdnn_inject_device_error", "sdnn_ckpt_size", "sdnn_create",
-           "sdnn_destroy", "sdnn_forward", "sdnn_get_plan", "sdnn_set_plan", "sdnn_layer", "sdnn_layer_backward", "sdnn_mse", "sdnn_schedule_host", "sdnn_set_exec", "sdnn_tune", "sdnn_set_timing", "sdnn_kernel_time",
+           "sdnn_destroy", "sdnn_forward", "sdnn_get_plan", "sdnn_set_plan", "sdnn_layer", "sdnn_layer_backward", "sdnn_mse", "sdnn_mse_noalloc", "sdnn_schedule_host", "sdnn_set_exec", "sdnn_tune", "sdnn_set_timing", "sdnn_kernel_time",
            "sdnn_version", "sdnn_workspace_size", "make_desc", "LIB_PATH"]

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <utility>
@@ -1222,6 +1223,57 @@ sdnn_status sdnn_mse(const float* y, const float* t, int64_t n, float* dy, float
         hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, s, (const float*)partial, (int32_t)MSE_BLOCKS, loss,
                            n ? 1.f / (float)n : 0.f);
     }
+    HIPCHK(hipGetLastError());
+    return SDNN_OK;
+}
+
+// ---------------------------------------------------------------- no-allocation MSE
+// sdnn_mse_noalloc keeps the per-workgroup partial sums in this file-scope device
+// array (each GPU the library runs on holds its own copy until the process ends)
+// instead of the caller's loss[1 .. MSE_BLOCKS].  Host code never passes the
+// array's name to a kernel: it is a host-side stand-in, not a device address.  The
+// device address comes from hipGetSymbolAddress, once per device, on the first call.
+constexpr int MSE_SCRATCH_FLOATS = 256;
+static_assert(MSE_BLOCKS <= MSE_SCRATCH_FLOATS, "the MSE partial sums must fit the static scratch");
+static __device__ __align__(256) float scratch[MSE_SCRATCH_FLOATS];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up on first use).
+sdnn_status scratch_address(float** out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+        return fail(SDNN_EUNSUPPORTED, "device ordinal %d is beyond the %d devices the static scratch serves", dev,
+                    SCRATCH_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(SDNN_EHIP, "hipGetSymbolAddress returned NULL for the MSE scratch on device %d", dev);
+        g_scratch_dev[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return SDNN_OK;
+}
+}  // namespace
+
+sdnn_status sdnn_mse_noalloc(const float* y, const float* t, int64_t n, float* dy, float* loss, void* stream) {
+    if (n < 0) return fail(SDNN_EINVAL, "n < 0");
+    if (n > 0 && (!y || !t)) return fail(SDNN_EINVAL, "y and t are required");
+    if (!dy && !loss) return SDNN_OK;
+    hipStream_t s = (hipStream_t)stream;
+    float* partial = nullptr;
+    if (loss) TRY(scratch_address(&partial));
+    // the same two kernels as sdnn_mse, so results are bitwise equal to it; every
+    // workgroup of k_mse writes its partial, so the scratch needs no clearing
+    hipLaunchKernelGGL(k_mse, dim3(MSE_BLOCKS), dim3(256), 0, s, y, t, n, dy, partial, n ? 2.f / (float)n : 0.f);
+    if (loss)
+        hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, s, (const float*)partial, (int32_t)MSE_BLOCKS, loss,
+                           n ? 1.f / (float)n : 0.f);
     HIPCHK(hipGetLastError());
     return SDNN_OK;
 }

@@ -56,6 +56,7 @@ PROTOTYPES = [
     ("sdnn_backward", _I32, [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
     ("sdnn_layer_backward", _I32, [_P, _I32, _P, _P, _P, _I64, _P, _P, _P, _P]),
     ("sdnn_mse", _I32, [_P, _P, _I64, _P, _P, _P]),
+    ("sdnn_mse_noalloc", _I32, [_P, _P, _I64, _P, _P, _P]),
     ("sdnn_schedule_host", _I32, [_P, _I32, _I32, _I32, _P, _P, _P]),
     ("sdnn_check_device", _I32, [_P, _P]),
     ("sdnn_inject_device_error", _I32, [_P, _I32, _P]),
@@ -186,6 +187,10 @@ def sdnn_layer_backward(h, layer, y_in, y_out, dy_out, rows, dw, dbias, dy_in=No
 
 def sdnn_mse(y, t, n, dy=None, loss=None, stream=None) -> None:
     _chk(lib().sdnn_mse(_ptr(y), _ptr(t), n, _ptr(dy), _ptr(loss), _stream(stream)), "sdnn_mse")
+
+
+def sdnn_mse_noalloc(y, t, n, dy=None, loss=None, stream=None) -> None:
+    _chk(lib().sdnn_mse_noalloc(_ptr(y), _ptr(t), n, _ptr(dy), _ptr(loss), _stream(stream)), "sdnn_mse_noalloc")
 
 
 def sdnn_schedule_host(idx, dmax: int = 44):
