@@ -89,6 +89,8 @@ typedef struct {
     int32_t threads;         /* workgroup size */
     int32_t grid;            /* workgroups per layer launch (grid-stride over tiles) */
     int32_t variant;         /* 2 = scheduled resident-weight kernel, 0 = LDS-staged rows,
+                                4 = one-row tiles with resident weights (forward-only nets of
+                                    2048 < N <= 16384 neurons, N % 4 == 0),
                                 1 = direct gather (rows too wide for LDS),
                                 3 = wide layers: rows packed T per tile [N][T] in the workspace,
                                     one T*4-byte gather per slot (forward-only nets whose

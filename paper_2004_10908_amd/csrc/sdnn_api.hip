@@ -66,6 +66,8 @@ struct Layout {
     bool sched = false;
     bool wide = false;
     size_t packed = 0, wide_words = 0;
+    bool row = false;
+    size_t row_words = 0;
     size_t tr_ptr = 0, tr_e = 0, seg = 0, gbuf0 = 0, gbuf1 = 0, pdw = 0, pdb = 0;
     size_t total = 0;
 };
@@ -100,6 +102,14 @@ bool sched_possible(const sdnn_desc& d) { return !(d.flags & SDNN_NO_SCHEDULE) &
 // scheduled kernel cannot take; their packed buffer holds every row once more.
 bool wide_possible(const sdnn_desc& d) { return !trainable(d) && !sched_shape(d); }
 
+// The one-row-tile kernel: a row of N floats fits one 64 KB LDS buffer (so every
+// 4-byte offset fits 16 bits), whole 16-byte copies (N % 4 == 0), and at least two
+// parts (below that the scheduled kernels serve the net).
+bool row_possible(const sdnn_desc& d) {
+    return !trainable(d) && d.n_neurons % 4 == 0 && d.n_neurons > ROW_PART && d.n_neurons <= ROW_NMAX;
+}
+int row_parts(const sdnn_desc& d) { return (d.n_neurons + ROW_PART - 1) / ROW_PART; }
+
 Layout make_layout(const sdnn_desc& d) {
     Layout y;
     size_t off = 0;
@@ -129,6 +139,8 @@ Layout make_layout(const sdnn_desc& d) {
         y.packed = take(rt * N * 4);
         y.wide_words = take(2 * ((R + WIDE_TMIN - 1) / WIDE_TMIN) * 4);
     }
+    y.row = row_possible(d);
+    if (y.row) y.row_words = take(R * 4);
     y.bar = take(NBAR * 4);
     y.fin = take(FIN_BLOCKS * 4);
     y.err = take(64);
@@ -233,6 +245,9 @@ struct sdnn_net_s {
     bool wide = false;                  // wide-layer kernels available (packed buffer present)
     float* packed = nullptr;
     int32_t* wide_words = nullptr;
+    bool row = false;                   // one-row-tile kernel available
+    int32_t* row_words = nullptr;
+    int row_parts = 0;
     uint32_t* ent = nullptr;
     int32_t *lane_neuron = nullptr, *wave_steps = nullptr, *tile_bits = nullptr, *prog = nullptr;
     int parts = 1, nblk = 0;
@@ -272,6 +287,7 @@ sdnn_status host_error(const sdnn_net_s* n) {
 }
 
 bool variant_fits(const sdnn_net_s* n, const FwdVariant& v) {
+    if (v.staged == 4) return n->row;
     if (v.staged == 3) return n->wide;
     if (v.staged == 2) return n->sched;
     if (!v.staged) return true;
@@ -282,6 +298,8 @@ bool variant_fits(const sdnn_net_s* n, const FwdVariant& v) {
 void fill_sched(const sdnn_net_s* n, LayerArgs& a, int l) {
     a.packed = n->packed;
     a.wide_words = n->wide_words;
+    a.row_words = n->row_words;
+    a.row_parts = n->row_parts;
     if (!n->sched) return;
     const size_t npad = (size_t)n->nblk * 64;
     a.ent = n->ent + (size_t)l * npad * SCHED_DSTORE;
@@ -318,6 +336,13 @@ sdnn_status prepare_variant(sdnn_net_s* n, int vi, int* grid, int* chain_grid) {
         *grid = SCHED_GRID;
         *chain_grid = SCHED_GRID;
     }
+    if (v.staged == 4) {
+        // one workgroup per CU, mapped to (XCD, part, stream) like the scheduled kernels
+        if (*grid < ROW_GRID || *chain_grid < ROW_GRID)
+            return fail(SDNN_EUNSUPPORTED, "one-row-tile kernel needs %d co-resident workgroups", ROW_GRID);
+        *grid = ROW_GRID;
+        *chain_grid = ROW_GRID;
+    }
     return SDNN_OK;
 }
 
@@ -328,6 +353,9 @@ int default_variant(const sdnn_net_s* n) {
     if (n->sched)
         for (int i = 0; i < fwd_variant_count(); ++i)
             if (fwd_variant(i).staged == 2) return i;
+    if (n->row)
+        for (int i = 0; i < fwd_variant_count(); ++i)
+            if (fwd_variant(i).staged == 4) return i;
     int best = -1, bestT = 0;
     for (int i = 0; i < fwd_variant_count(); ++i) {
         const FwdVariant& v = fwd_variant(i);
@@ -540,6 +568,8 @@ Plan plan_persistent(const sdnn_net_s* n, const float* y0, int64_t rows, float* 
     }
     c.packed = n->packed;
     c.wide_words = n->wide_words;
+    c.row_words = n->row_words;
+    c.row_parts = n->row_parts;
     auto ch = mk(v.chain_fn, dim3(n->chain_grid), dim3(v.NT), sh, c);
     ch->cooperative = true;
     ch->timed = true;
@@ -678,6 +708,11 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
         n->packed = (float*)(n->ws + lay.packed);
         n->wide_words = (int32_t*)(n->ws + lay.wide_words);
     }
+    if (lay.row) {
+        n->row = true;
+        n->row_words = (int32_t*)(n->ws + lay.row_words);
+        n->row_parts = row_parts(*desc);
+    }
     HIPCHK(hipGetDevice(&n->device));
     HIPCHK(hipDeviceGetAttribute(&n->num_cu, hipDeviceAttributeMultiprocessorCount, n->device));
     {
@@ -704,6 +739,10 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
     if (n->wide) {
         const int64_t nw = 2 * ((std::max<int64_t>(desc->max_rows, 1) + WIDE_TMIN - 1) / WIDE_TMIN);
         hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nw)), dim3(256), 0, s, n->wide_words, nw, 0);
+    }
+    if (n->row) {
+        const int64_t nw = std::max<int64_t>(desc->max_rows, 1);
+        hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nw)), dim3(256), 0, s, n->row_words, nw, 0);
     }
     HIPCHK(hipGetLastError());
     if (desc->flags & SDNN_DEBUG_CHECKS) {

@@ -1,0 +1,95 @@
+// Device helpers shared by the forward kernel files: the acquire load of a
+// device counter, the persistent kernels' grid barrier and the per-layer
+// arguments of the persistent chain.
+#pragma once
+
+#include "sdnn_internal.hpp"
+
+namespace sdnn {
+
+__device__ __forceinline__ int ld_acquire(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------- grid barrier
+// Two-level arrive counter: workgroups arrive on one of 8 group counters
+// (blockIdx % 8, the XCD a workgroup is dispatched to), the last of each group
+// arrives on the root, the last at the root bumps the generation word that every
+// workgroup polls.  Counters return to zero after each barrier.  Waits are
+// bounded by the 100 MHz real-time counter; a time-out, or an error raised by
+// any other workgroup, makes every waiter leave with `false`.
+// bar layout (one 128-byte line each): [g*32] group g, [8*32] root, [9*32] generation.
+
+
+__device__ inline bool grid_barrier(unsigned* bar, unsigned& gen, int32_t* err, int* s_ok_ptr) {
+    int& s_ok = *s_ok_ptr;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned nwg = gridDim.x;
+        const unsigned g = blockIdx.x & 7u;
+        const unsigned ngroups = nwg < 8u ? nwg : 8u;
+        const unsigned gsize = (nwg - g + 7u) / 8u;
+        const unsigned target = gen + 1u;
+        int ok = 1;
+        __threadfence();
+        const unsigned old = atomicAdd(&bar[g * 32], 1u);
+        if (old == gsize - 1u) {
+            atomicExch(&bar[g * 32], 0u);
+            const unsigned o2 = atomicAdd(&bar[8 * 32], 1u);
+            if (o2 == ngroups - 1u) {
+                atomicExch(&bar[8 * 32], 0u);
+                __threadfence();
+                atomicExch(&bar[9 * 32], target);
+            }
+        }
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        while (__hip_atomic_load(&bar[9 * 32], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = 0; break; }
+            if (__builtin_amdgcn_s_memrealtime() - t0 > 1000000000ull) {   // 10 s at 100 MHz
+                atomicExch(err, (int32_t)DEV_BARRIER_TIMEOUT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __threadfence();
+        gen = target;
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// ---------------------------------------------------------------- persistent chain arguments
+// Layer l of the persistent chain writes X_l, which is y_out when (L-1-l) is even
+// and the workspace buffer otherwise, so the last layer always lands in y_out.
+__device__ __forceinline__ LayerArgs chain_layer_args(const ChainArgs& c, int l, int R) {
+    const int N = c.N, L = c.L;
+    const size_t NK = (size_t)N * K;
+    const bool out_is_y = ((L - 1 - l) & 1) == 0;
+    LayerArgs a{};
+    a.yin = l == 0 ? c.y0 : (out_is_y ? c.act : c.y_out);
+    a.yout = out_is_y ? c.y_out : c.act;
+    a.ycopy = (c.ckpt && (l + 1) % c.ckpt_every == 0 && l + 1 < L)
+                  ? c.ckpt + (size_t)((l + 1) / c.ckpt_every - 1) * c.rows * N
+                  : nullptr;
+    a.dead_mark = (c.compaction && !out_is_y) ? -1 : 0;
+    a.idx = c.idx + l * NK;
+    a.w = c.w + l * NK;
+    a.b = c.b + (size_t)l * N;
+    a.list_in = (l == 0 || !c.compaction) ? nullptr : ((l & 1) ? c.list1 : c.list0);
+    a.list_out = c.compaction ? (((l + 1) & 1) ? c.list1 : c.list0) : nullptr;
+    a.cnt_in = nullptr;
+    a.cnt_out = &c.cnt[l + 1];
+    a.alive = c.alive;
+    a.row_base = 0;
+    a.nrows = R;
+    a.N = N;
+    a.layer = l;
+    a.clamp = c.clamp;
+    a.packed = c.packed;
+    a.wide_words = c.wide_words;
+    return a;
+}
+
+}  // namespace sdnn

@@ -51,6 +51,10 @@ struct LayerArgs {
     // (row bits, workgroups done), zero between layers
     float* packed;
     int32_t* wide_words;
+    // one-row-tile kernel only: one word per work-list position (parts done << 16 |
+    // parts with a nonzero output), zero between layers
+    int32_t* row_words;
+    int32_t row_parts;           // G: parts of ROW_PART neurons sharing a row
 };
 
 // Scheduled weight-gradient pass over one layer (rows are compact 0..R-1).
@@ -130,6 +134,9 @@ struct ChainArgs {
     // wide-layer kernels only
     float* packed;
     int32_t* wide_words;
+    // one-row-tile kernel only
+    int32_t* row_words;
+    int32_t row_parts;
 };
 
 // Error codes written to the device error word.
@@ -139,7 +146,8 @@ enum DeviceError : int32_t { DEV_OK = 0, DEV_BARRIER_TIMEOUT = 1 };
 struct FwdVariant {
     int T;          // rows per tile
     int NT;         // threads per workgroup
-    int staged;     // 3 = wide (packed row tiles), 2 = scheduled resident-weight kernel,
+    int staged;     // 4 = one-row tiles (resident weights), 3 = wide (packed row tiles),
+                    // 2 = scheduled resident-weight kernel,
                     // 1 = rows staged in LDS, 0 = direct gather
     const void* layer_fn;    // __global__ void(LayerArgs)
     const void* chain_fn;    // __global__ void(ChainArgs)  (cooperative)
@@ -150,9 +158,24 @@ struct FwdVariant {
 constexpr int WIDE_TMIN = 8;
 constexpr int WIDE_TMAX = 32;
 constexpr int WIDE_PACK_NT = 256;    // threads of the pack kernel
+// The one-row-tile resident-weight kernel (sdnn_row.hip): a workgroup of ROW_NT
+// lanes owns ROW_PART neurons (two per lane, ids and weights in registers) and
+// stages one activation row at a time in LDS; ceil(N / ROW_PART) parts share a row.
+constexpr int ROW_NT = 1024;
+constexpr int ROW_PART = 2048;
+constexpr int ROW_NMAX = 16384;                          // the row (4 N bytes) fits one 64 KB buffer
+constexpr uint32_t ROW_BUF_BYTES = 65536;                // two row buffers at 0 and 65536
+constexpr uint32_t ROW_STAGE = 2 * ROW_BUF_BYTES;        // two output stages of ROW_PART floats
+constexpr uint32_t ROW_SCAL = ROW_STAGE + 2 * ROW_PART * 4;
+constexpr size_t ROW_LDS = ROW_SCAL + 256;
+constexpr int ROW_GRID = 256;                            // one workgroup per CU, 8 XCDs x 32
+__global__ void k_layer_row(LayerArgs a);
+__global__ void k_chain_row(ChainArgs c);
+
 int fwd_variant_count();
 const FwdVariant& fwd_variant(int i);
 inline size_t fwd_lds_bytes(const FwdVariant& v, int N) {
+    if (v.staged == 4) return ROW_LDS;
     return v.staged == 2 ? sched_lds_bytes(N) : (v.staged == 1 ? (size_t)v.T * N * sizeof(float) : 0);
 }
 

@@ -35,10 +35,10 @@ def test_wide_forward_matches_oracle(P, N, layers, rows):
     y0h = gen.make_inputs(cfg)
     y0 = torch.from_numpy(y0h).to(DEV)
     net = P.Net(idx, w, b, max_rows=rows, ckpt_every=1)
-    if 2 * N * 4 > 160 * 1024:
-        assert net.plan["variant"] == 3, net.plan    # not even 2 LDS rows fit: the wide kernel is the default
+    if N > 16384:
+        assert net.plan["variant"] == 3, net.plan    # a row exceeds one 64 KB LDS buffer: the wide kernel
     else:
-        assert net.plan["variant"] == 0, net.plan    # LDS row tiles where 2 or more fit
+        assert net.plan["variant"] == 4, net.plan    # one-row tiles with resident weights
         net.set_plan(32, 1024, 3)
     base = None
     for m in MODES:
@@ -51,9 +51,9 @@ def test_wide_forward_matches_oracle(P, N, layers, rows):
     net.close()
 
 
-# Several tiles per workgroup (grid-stride LDS kernel at 16384 neurons) and per XCD
-# tile stream (wide kernel at 65536 neurons), every layer of the chain checked
-# element by element through its own activations.
+# Several tiles per workgroup (one-row-tile kernel at 16384 neurons, and the wide
+# kernel on the same net) and per XCD tile stream (wide kernel at 65536 neurons),
+# every layer of the chain checked element by element through its own activations.
 @pytest.mark.parametrize("N,layers,rows,plan", [(16384, 8, 2400, None), (16384, 6, 2400, (32, 1024, 3)),
                                                 (65536, 6, 1200, None)])
 def test_wide_chain_layer_sync_multi_tile(P, N, layers, rows, plan):
@@ -89,7 +89,7 @@ def test_wide_variants_bitwise_equal(P):
     off = [0, 40, 40, 41, 200, rows]
     net = P.Net(idx, w, b, max_rows=rows, ckpt_every=1)
     base = None
-    for T, NT, v in [(4, 512, 0)] + WIDE:
+    for T, NT, v in [(4, 512, 0), (1, 1024, 4)] + WIDE:
         plan = net.set_plan(T, NT, v)
         assert (plan["rows_per_tile"], plan["threads"], plan["variant"]) == (T, NT, v)
         for m in ("graph", "persistent"):
@@ -103,7 +103,7 @@ def test_wide_variants_bitwise_equal(P):
     net.close()
 
 
-@pytest.mark.parametrize("T,NT,v", WIDE)
+@pytest.mark.parametrize("T,NT,v", WIDE + [(1, 1024, 4)])
 def test_wide_layer_sync_clamp_and_positive_bias(P, T, NT, v):
     """Layer by layer with a clamp the sums reach and a positive bias (compaction
     off), then the whole forward in every mode."""
