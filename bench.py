@@ -1,19 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark of the layered sparse-DNN forward on one MI355X.
 
-Workload (the metric's configuration): 4096 neurons x 480 layers, 32 inputs per
-neuron (weights 1/16, bias -0.35, clip 32), 60000 Bernoulli(0.2) binary input
-rows, plain forward in fp32, drawn by the seeded generator in sdnn_inputs (seed 2).
-A step is one sdnn_forward over all 60000 rows and all 480 layers, with the
-network and the inputs resident in HBM.  The metric is edges/s =
-rows x nnz(W) / step time.
+Workload (the metric's configuration): the batched forward at the largest shape
+one GPU holds, 65536 neurons x 1920 layers (4.03e9 nonzeros, int32 ids + fp32
+weights, 32 GB resident), 32 inputs per neuron (weights 1/16, bias -0.45, clip
+32), 15000 Bernoulli(0.2) binary input rows in 20 uneven batches of 250..4000 rows,
+all batches in one pass (one persistent launch or one merged graph), fp32, drawn by
+the seeded device generator of sdnn_inputs (seed 4).  A step is one sdnn_forward
+over all 15000 rows and all 1920 layers, with the network and the inputs resident
+in HBM.  The metric is edges/s = rows x nnz(W) / step time.
 
 Prints ONE JSON line.  Besides the required fields it carries:
   roofline      the dominant kernel's algorithmic HBM bytes per launch / its
-                average duration, against MI355X's 8 TB/s
+                average duration (HIP events on the library's own stream),
+                against MI355X's 8 TB/s; traffic from committed rocprofv3 counters
   cpu_baseline  the FP64 oracle timed on this host on a bounded row sample
-  extras        sustained (S2), batched vs plain (C3), bwd/fwd ratio (G5),
-                engine comparison and a full-live layer, when --extras is on
+                (all host threads, and one thread on a smaller sample)
+  extras        the plain form (batches one after another) of the same workload,
+                the tuned and default plans, and, with --extras: the C2 plain
+                forward, a full-live C2 layer, S2 (sustained), C3 and S3 batched vs
+                plain, S4 (sustained at 65536 neurons), the G5 bwd/fwd ratio
   streams       with --streams C3,S2_20,C4: the stream/graph forms of the batched
                 forward (explicit graph, eager and captured over 1-8 streams)
   streamed      with --streamed: parameters in pinned host memory streamed through
@@ -40,6 +46,8 @@ K = 32
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--config", default="C4", choices=["C4", "C2"],
+                    help="headline workload: C4 (batched, 65536 x 1920) or C2 (plain, 4096 x 480)")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--engine", default="auto", choices=["auto", "graph", "persistent", "eager"],
@@ -48,7 +56,8 @@ def parse():
     ap.add_argument("--no-extras", dest="extras", action="store_false")
     ap.add_argument("--cpu", dest="cpu", action="store_true", default=True)
     ap.add_argument("--no-cpu", dest="cpu", action="store_false")
-    ap.add_argument("--cpu-rows", type=int, default=15000, help="row sample for the oracle baseline (about 12 s)")
+    ap.add_argument("--cpu-rows", type=int, default=15000, help="row sample for the oracle baseline (all threads)")
+    ap.add_argument("--cpu-rows1", type=int, default=400, help="row sample for the one-thread oracle baseline")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (the reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale) and exit")
@@ -79,29 +88,47 @@ def forward_bytes(prof, N, L):
     return tot
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_chain_sched_C2_forward.md")
+# committed rocprofv3 counter summaries of the persistent chain kernels, per
+# headline workload: (summary, kernel source it was taken with)
+PROFILES = {"C4": ("k_chain_wide_C4_forward.md", "sdnn_fwd.hip"),
+            "C2": ("k_chain_sched_C2_forward.md", "sdnn_fwd.hip")}
 
 
-def measured_traffic():
+def measured_traffic(workload, kernel):
     """HBM bytes per launch of the persistent chain kernel from its committed
-    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source has
-    changed since those counters were taken (or there is no summary)."""
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the summary is for another
+    kernel or the kernel source has changed since those counters were taken."""
     import hashlib
+    if workload not in PROFILES:
+        return None
+    summary, src = PROFILES[workload]
     try:
-        text = open(PROFILE).read()
+        text = open(os.path.join(ROOT, "profiles", summary)).read()
     except OSError:
         return None
     vals = {}
     for line in text.splitlines():
         k, _, v = line.strip().partition(": ")
-        if k in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+        if k in ("traffic_bytes_per_launch", "kernel_source_sha256", "kernel"):
             vals[k] = v.strip()
-    if len(vals) != 2:
+    if len(vals) != 3 or vals["kernel"] != kernel:
         return None
-    src = os.path.join(ROOT, "paper_2004_10908_amd", "csrc", "sdnn_fwd.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != vals["kernel_source_sha256"]:
+    path = os.path.join(ROOT, "paper_2004_10908_amd", "csrc", src)
+    if hashlib.sha256(open(path, "rb").read()).hexdigest() != vals["kernel_source_sha256"]:
         return None
     return int(vals["traffic_bytes_per_launch"])
+
+
+def chain_kernel_name(plan):
+    """Name of the persistent chain kernel a plan runs (as rocprofv3 reports it)."""
+    T, NT, v = plan["rows_per_tile"], plan["threads"], plan["variant"]
+    if v == 2:
+        return "sdnn::k_chain_sched<512, 40>"
+    if v == 3:
+        return f"sdnn::k_chain_wide<{T}, {NT}>"
+    if v == 4:
+        return "sdnn::k_chain_row"
+    return f"sdnn::k_chain<{T}, {NT}, {'true' if v == 0 else 'false'}>"
 
 
 def live_edges(prof, N, L):
@@ -152,28 +179,45 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": n * 4, "launches": 5}))
         return
 
-    cfg = gen.CONFIGS["C2"]
+    name = args.config
+    cfg = gen.CONFIGS[name]
     N, L, B = cfg.n_neurons, cfg.n_layers, cfg.rows
     nnz = cfg.nnz
     t0 = time.time()
-    idx_h, w_h, b_h = gen.make_net(cfg)
-    y0_h = gen.make_inputs(cfg)
-    log(f"generated C2 in {time.time() - t0:.1f}s")
-    idx, w, b = (torch.from_numpy(a).to(dev) for a in (idx_h, w_h, b_h))
-    y0 = torch.from_numpy(y0_h).to(dev)
+    idx, w, b = device_net(torch, gen, cfg, dev)
+    y0 = device_inputs(torch, cfg, dev)
+    off = [int(v) for v in gen.make_batches(cfg)] if cfg.n_batches > 1 else None
+    torch.cuda.synchronize()
+    log(f"generated {name} in {time.time() - t0:.1f}s")
     net = P.Net(idx, w, b, max_rows=B)
-    if args.tune:
-        plan = net.tune(8192)
-        log("tuned plan", plan)
+    default_plan = net.plan
+    batched = off is not None
     out = {}
-    net.forward(y0, out=out, profile=True)
+    net.forward(y0, batch_off=off, out=out, profile=True)
+    extras = {"default_plan": default_plan}
+    if args.tune:
+        # the autotuner times every variant of the net's kernel family on the
+        # workload's own rows (one full-live layer of the persistent chain kernel)
+        rows0 = B
+        eng0 = "persistent"
+        net.set_exec(eng0)
+        extras["default_plan_ms"] = round(time_forward(torch, net, y0, out, 3, 1, batch_off=off), 4)
+        t1 = time.time()
+        plan = net.tune(rows0, y_sample=y0[:rows0])
+        extras["tune_seconds"] = round(time.time() - t1, 2)
+        extras["tuned_plan"] = plan
+        extras["tuned_plan_ms"] = round(time_forward(torch, net, y0, out, 3, 1, batch_off=off), 4)
+        log("default plan", default_plan, extras["default_plan_ms"], "ms; tuned plan", plan,
+            extras["tuned_plan_ms"], "ms")
 
-    # engine choice (warm-up): graph vs persistent
+    # engine choice (warm-up): the batched forms (persistent launch, merged graph), or
+    # for one batch the graph and the persistent launch
     engines = {}
-    cands = ["graph", "persistent"] if args.engine == "auto" else [args.engine]
+    cands = (["persistent", "graph_merged"] if batched else ["graph", "persistent"]) \
+        if args.engine == "auto" else [args.engine]
     for eng in cands:
         net.set_exec(eng)
-        engines[eng] = time_forward(torch, net, y0, out, max(2, args.warmup), 1)
+        engines[eng] = time_forward(torch, net, y0, out, max(2, args.warmup), 1, batch_off=off)
     engine = min(engines, key=engines.get)
     net.set_exec(engine)
     log("warm-up engine times (ms)", engines, "->", engine)
@@ -184,7 +228,7 @@ def main():
     timed_kernel = engine == "persistent"
     if timed_kernel:
         net.set_timing(True)
-    ms = time_forward(torch, net, y0, out, args.steps, args.warmup,
+    ms = time_forward(torch, net, y0, out, args.steps, args.warmup, batch_off=off,
                       on_start=(lambda: net.kernel_time()) if timed_kernel else None)   # drop warm-up events
     k_ms, k_n = net.kernel_time() if timed_kernel else (0.0, 0)
     if timed_kernel:
@@ -194,60 +238,70 @@ def main():
     n_nz = int(out["n_nz"].item())
     value = B * nnz / (ms / 1e3)
     alg = forward_bytes(prof, N, L)
+    plan = net.plan
     if timed_kernel:
-        kernel = "sdnn::k_chain_sched<512, 40> (persistent forward, all layers, one launch per step)"
+        kernel = chain_kernel_name(plan)
         alg_launch, dur_ms = alg, k_avg
+        kdesc = kernel + " (persistent forward: all layers of all batches, one launch per step)"
     else:
-        kernel = "sdnn::k_layer_sched<512, 40> (one graph node per layer; step time / layers)"
+        kernel = None
         alg_launch, dur_ms = alg / L, ms / L
+        kdesc = f"layer kernel of plan {plan} (one graph node per layer; step time / layers)"
     achieved = alg_launch / (dur_ms / 1e3) / 1e9
-    tb = measured_traffic() if timed_kernel else None
+    tb = measured_traffic(name, kernel) if timed_kernel else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": round(tb / (dur_ms / 1e3) / 1e9, 1) if tb else None,
-                "traffic_bytes_per_launch": tb, "kernel": kernel,
+                "traffic_bytes_per_launch": tb, "kernel": kdesc,
                 "alg_bytes_per_launch": alg_launch, "avg_launch_ms": round(dur_ms, 4)}
-    log(f"C2 {engine}: {ms:.3f} ms/step, {value:.3e} edges/s, profile head {prof[:5].tolist()}, nz {n_nz}")
-
-    extras = {"engines_ms": {k: round(v, 4) for k, v in engines.items()}, "plan": net.plan,
-              "c2_profile_head": prof[:6].tolist(), "c2_live_edges_per_s": live_edges(prof, N, L) / (ms / 1e3),
-              "c2_alg_bytes": alg}
+    log(f"{name} {engine}: {ms:.3f} ms/step, {value:.3e} edges/s, profile head {prof[:5].tolist()}, nz {n_nz}")
+    extras.update({"engines_ms": {k: round(v, 4) for k, v in engines.items()}, "plan": plan,
+                   "profile_head": prof[:6].tolist(), "live_edges_per_s": live_edges(prof, N, L) / (ms / 1e3),
+                   "alg_bytes": alg})
+    if batched:
+        # the plain form of the same workload: the batches one after another through
+        # the layer graph
+        net.set_exec("graph")
+        pms = time_forward(torch, net, y0, out, 2, 1, batch_off=off)
+        extras["plain_ms"] = round(pms, 3)
+        extras["plain_edges_per_s"] = B * nnz / (pms / 1e3)
+        extras["batched_over_plain"] = round(pms / ms, 3)
+        log(f"{name} plain (graph, batches in turn): {pms:.3f} ms")
+    net.close()
+    del idx, w, b, out
+    torch.cuda.empty_cache()
 
     # ---------------------------------------------------------------- extras
     if args.extras:
         try:
-            extras.update(bench_extras(args, torch, np, P, gen, dev, net, y0, idx, w, b))
+            extras.update(bench_extras(args, torch, np, P, gen, dev))
         except Exception as e:  # extras never hide the headline
             extras["error"] = repr(e)
             log("extras failed:", repr(e))
     if args.streams:
-        net.close()
-        torch.cuda.empty_cache()
         extras["streams"] = bench_streams(args, torch, P, gen, dev)
     if args.streamed:
-        net.close()
-        torch.cuda.empty_cache()
         extras["streamed"] = bench_streamed(args, torch, P, gen, dev)
     if args.table:
-        net.close()
-        torch.cuda.empty_cache()
         extras["table"] = bench_table(args, torch, P, gen, dev)
-    net.close()
-    del y0, idx, w, b, out
-    torch.cuda.empty_cache()
 
     cpu = None
     if args.cpu:
         try:
-            cpu = cpu_baseline(args, np, gen, cfg, idx_h, w_h, b_h, y0_h)
+            cpu = cpu_baseline(args, np, gen, cfg, y0, off)
         except Exception as e:
             log("cpu baseline failed:", repr(e))
+    del y0
+    torch.cuda.empty_cache()
 
+    desc = (f"{name} {'batched' if batched else 'plain'} forward: {N} neurons x {L} layers, k=32, "
+            f"{'w=1/16' if cfg.weight == 'const' else cfg.weight + ' weights'}, b={cfg.bias}, clip {cfg.clamp:g}, "
+            f"{B} Bernoulli({cfg.density:g}) rows" + (f" in {len(off) - 1} uneven batches" if batched else "")
+            + f", seed {cfg.seed}")
     line = {"metric": "edges/s (inputs x nnz(W) / s)", "value": value, "unit": "edges/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
-            "config": {"workload": "C2 plain forward: 4096 neurons x 480 layers, k=32, w=1/16, b=-0.35, clip 32, "
-                                   "60000 Bernoulli(0.2) rows, seed 2", "global_batch": B, "seq_len": None,
+            "config": {"workload": desc, "global_batch": B, "seq_len": None,
                        "parallelism": "single-gpu", "engine": engine},
             "roofline": roofline, "cpu_baseline": cpu, "extras": extras}
     print(json.dumps(line), flush=True)
@@ -291,23 +345,46 @@ def device_inputs(torch, cfg, dev):
     return (torch.rand((cfg.rows, cfg.n_neurons), generator=g, device=dev) < p).float()
 
 
-def bench_extras(args, torch, np, P, gen, dev, net_c2, y0_c2, idx2, w2, b2):
+def bench_extras(args, torch, np, P, gen, dev):
     ex = {}
-    N = 4096
-    # full-live layer of C2's shape (every row alive): the gather kernel's steady-state rate
-    ms = full_live_layer(torch, net_c2, y0_c2)
-    byt = 8 * N * K + 4 * N + 8 * y0_c2.shape[0] * N
-    ex["full_live_layer"] = {"rows": y0_c2.shape[0], "ms": round(ms, 4), "alg_GBps": round(byt / ms / 1e6, 1),
-                             "frac": round(byt / ms / 1e6 / HBM_PEAK_GBS, 4),
-                             "edges_per_s": y0_c2.shape[0] * N * K / (ms / 1e3)}
-    log("full-live layer", ex["full_live_layer"])
-
-    # S2: sustained companion (rows stay alive), device-drawn net and inputs
-    cfg = gen.CONFIGS["S2"]
+    # C2: the plain forward of 4096 neurons x 480 layers, 60000 rows (the scheduled
+    # resident-weight kernel), and a full-live layer of its shape (every row alive):
+    # the kernel's steady-state rate
+    cfg = gen.CONFIGS["C2"]
+    N = cfg.n_neurons
     idx, w, b = device_net(torch, gen, cfg, dev)
     y0 = device_inputs(torch, cfg, dev)
     net = P.Net(idx, w, b, max_rows=cfg.rows)
-    net.plan_ = net.tune(8192)
+    o = {}
+    net.forward(y0, out=o, profile=True)
+    res = {"plan": net.plan}
+    for eng in ("graph", "persistent"):
+        net.set_exec(eng)
+        ms = time_forward(torch, net, y0, o, 5, 2)
+        prof = o["layer_rows"].cpu().numpy()
+        alg = forward_bytes(prof, N, cfg.n_layers)
+        res[eng] = {"ms": round(ms, 4), "edges_per_s": cfg.rows * cfg.nnz / (ms / 1e3),
+                    "live_edges_per_s": live_edges(prof, N, cfg.n_layers) / (ms / 1e3),
+                    "frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    res["profile_head"] = prof[:5].tolist()
+    ms = full_live_layer(torch, net, y0)
+    byt = 8 * N * K + 4 * N + 8 * y0.shape[0] * N
+    res["full_live_layer"] = {"rows": y0.shape[0], "ms": round(ms, 4), "alg_GBps": round(byt / ms / 1e6, 1),
+                              "frac": round(byt / ms / 1e6 / HBM_PEAK_GBS, 4),
+                              "edges_per_s": y0.shape[0] * N * K / (ms / 1e3)}
+    ex["C2"] = res
+    log("C2", res)
+    net.close()
+    del idx, w, b, y0, o
+    torch.cuda.empty_cache()
+
+    # S2: sustained companion (rows stay alive), device-drawn net and inputs
+    cfg = gen.CONFIGS["S2"]
+    N = cfg.n_neurons
+    idx, w, b = device_net(torch, gen, cfg, dev)
+    y0 = device_inputs(torch, cfg, dev)
+    net = P.Net(idx, w, b, max_rows=cfg.rows)
+    net.tune(cfg.rows, y_sample=y0)
     o = {}
     net.forward(y0, out=o, profile=True)
     res = {}
@@ -326,25 +403,36 @@ def bench_extras(args, torch, np, P, gen, dev, net_c2, y0_c2, idx2, w2, b2):
     del idx, w, b, y0, o
     torch.cuda.empty_cache()
 
-    # C3: batched (one pass over all 20 uneven batches) vs plain (batches one after another)
-    for name in ("C3", "S3"):
+    # C3 / S3 / S4: batched (one pass over all 20 uneven batches) vs plain (batches one
+    # after another); the plan tuned on the first batch against the default one
+    for name in ("C3", "S3", "S4"):
         cfg = gen.CONFIGS[name]
+        N, L = cfg.n_neurons, cfg.n_layers
         idx, w, b = device_net(torch, gen, cfg, dev)
         y0 = device_inputs(torch, cfg, dev)
         off = [int(v) for v in gen.make_batches(cfg)]
         net = P.Net(idx, w, b, max_rows=cfg.rows)
         o = {}
         net.forward(y0, out=o, profile=True)
-        r = {}
-        for eng in ("graph", "graph_merged", "persistent"):
-            net.set_exec(eng)
-            ms = time_forward(torch, net, y0, o, 2 if name == "S3" else 3, 1, batch_off=off)
-            r[eng] = {"ms": round(ms, 3), "edges_per_s": cfg.rows * cfg.nnz / (ms / 1e3)}
+        r = {"default_plan": net.plan}
+        reps = 1 if name == "S4" else (2 if name == "S3" else 3)
+        net.set_exec("persistent")
+        r["default_plan_persistent_ms"] = round(time_forward(torch, net, y0, o, reps, 1, batch_off=off), 3)
+        r["tuned_plan"] = net.tune(cfg.rows, y_sample=y0)
         prof = o["layer_rows"].cpu().numpy()
-        r["plain"] = "graph (batches one after another)"
+        alg = forward_bytes(prof, N, L)
+        forms = ("persistent", "graph_merged") if name == "S4" else ("graph", "graph_merged", "persistent")
+        for eng in forms:
+            net.set_exec(eng)
+            ms = time_forward(torch, net, y0, o, reps, 1, batch_off=off)
+            r[eng] = {"ms": round(ms, 3), "edges_per_s": cfg.rows * cfg.nnz / (ms / 1e3),
+                      "live_edges_per_s": live_edges(prof, N, L) / (ms / 1e3),
+                      "frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)}
         r["batched_best"] = max(("graph_merged", "persistent"), key=lambda k: r[k]["edges_per_s"])
-        r["batched_over_plain"] = r[r["batched_best"]]["edges_per_s"] / r["graph"]["edges_per_s"]
-        r["alive_profile"] = [int(v) for v in prof[[0, 1, 2, 5, 10, 100, 479, 480]]]
+        if "graph" in r:
+            r["plain"] = "graph (batches one after another)"
+            r["batched_over_plain"] = r[r["batched_best"]]["edges_per_s"] / r["graph"]["edges_per_s"]
+        r["alive_profile"] = [int(prof[i]) for i in (0, 1, 2, 5, 10, 100, L - 1, L)]
         ex[name] = r
         log(name, r)
         net.close()
@@ -536,18 +624,59 @@ def bench_table(args, torch, P, gen, dev):
     return res
 
 
-def cpu_baseline(args, np, gen, cfg, idx_h, w_h, b_h, y0_h):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(args, np, gen, cfg, y0, off):
+    """The FP64 oracle (plain C, OpenMP over rows) on this host: every host thread on
+    a row sample of the same workload, and one thread on a smaller sample.  Its
+    layers come from the same device generator as the GPU run's (generated before
+    the timed part); it runs layers 0, 1, ... until its own count of alive rows is
+    zero, after which the remaining layers receive no rows (every bias is <= 0) and
+    add no work, exactly as the GPU's early exit."""
     import oracle
+    import torch
     oracle.build()
+    dev = y0.device
     rows = min(args.cpu_rows, cfg.rows)
-    sample = y0_h[:rows]
-    layers = [(idx_h[l], w_h[l], b_h[l]) for l in range(cfg.n_layers)]
+    sample = y0[:rows].cpu().numpy()
+    layers = []
+
+    def grow(n):
+        while len(layers) < min(n, cfg.n_layers):
+            i_, w_, b_ = gen.make_layer_device(cfg, len(layers), dev)
+            layers.append((i_.cpu().numpy(), w_.cpu().numpy(), b_.cpu().numpy()))
+
+    threads = oracle.max_threads()
+    n_layers = 2
+    while True:
+        grow(n_layers)
+        t0 = time.perf_counter()
+        res = oracle.forward(layers, sample, cfg.clamp, threads=threads)
+        dt = time.perf_counter() - t0
+        if res.alive_after[-1] == 0 or len(layers) == cfg.n_layers:
+            break
+        n_layers *= 2                               # not extinct yet: more layers, time again
+    last = len(layers)
+    rows1 = max(1, min(rows, args.cpu_rows1))
     t0 = time.perf_counter()
-    oracle.forward(layers, sample, cfg.clamp)
-    dt = time.perf_counter() - t0
-    return {"value": rows * cfg.nnz / dt, "unit": "edges/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"first {rows} of the 60000 C2 rows through all 480 layers (FP64, {dt:.1f} s)",
-            "seconds": round(dt, 2)}
+    oracle.forward(layers, sample[:rows1], cfg.clamp, threads=1)
+    dt1 = time.perf_counter() - t0
+    ext = (f"every row is dead after layer {last - 1} (the oracle's own count), so layers {last}..{cfg.n_layers - 1} "
+           "receive no rows" if res.alive_after[-1] == 0 else "all layers")
+    return {"value": rows * cfg.nnz / dt, "unit": "edges/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first {rows} of the {cfg.rows} {cfg.name} rows through layers 0..{last - 1}; {ext} "
+                      f"(FP64, {threads} threads, {dt:.1f} s)",
+            "seconds": round(dt, 2), "cpu_model": cpu_model(), "alive_after": [int(a) for a in res.alive_after],
+            "single_thread": {"value": rows1 * cfg.nnz / dt1, "unit": "edges/s", "rows": rows1,
+                              "seconds": round(dt1, 2)}}
 
 
 if __name__ == "__main__":

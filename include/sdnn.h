@@ -145,9 +145,17 @@ sdnn_status sdnn_set_plan(sdnn_net net, const sdnn_plan *plan);
 sdnn_status sdnn_set_timing(sdnn_net net, int32_t enable);
 sdnn_status sdnn_kernel_time(sdnn_net net, double *total_ms, int32_t *launches);
 
-/* Time every kernel variant that fits on a full-live layer of `rows` rows (rows <=
- * max_rows; uses the workspace as scratch) and keep the fastest.  Synchronizes. */
-sdnn_status sdnn_tune(sdnn_net net, int64_t rows, void *stream);
+/* Autotuner of the layer kernel's tile plan (rows per tile, workgroup size, kernel
+ * form; the paper leaves the GPU kernel's shape open, section "Large Sparse Neural
+ * Network Inference").  Times layer 0 over `rows` rows with every kernel variant of
+ * the net's family that fits (variants of one family sum each output in the same
+ * order, so the choice never changes results) and keeps the fastest; its time per
+ * layer is reported as sdnn_plan.tuned_us.
+ *   y_sample  dev fp32 [rows][N]: rows of the workload (e.g. the first batch), rows <=
+ *             max_rows; or NULL: all-ones rows, min(rows, max_rows / 2) of them
+ * Uses the workspace as scratch (a later forward rewrites it).  Synchronizes.
+ * SDNN_EINVAL for rows < 0 or rows > max_rows with a sample. */
+sdnn_status sdnn_tune(sdnn_net net, const float *y_sample, int64_t rows, void *stream);
 
 /*
  * Forward pass over `rows` input rows.

@@ -866,7 +866,7 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
     HIPCHK(hipStreamSynchronize(s));
     sdnn_net net = n.release();
     if (desc->flags & SDNN_AUTOTUNE) {
-        const sdnn_status st = sdnn_tune(net, desc->max_rows, stream);
+        const sdnn_status st = sdnn_tune(net, nullptr, desc->max_rows, stream);
         if (st != SDNN_OK) {
             sdnn_destroy(net);
             return st;
@@ -935,22 +935,34 @@ sdnn_status sdnn_set_plan(sdnn_net net, const sdnn_plan* plan) {
                 plan->variant);
 }
 
-sdnn_status sdnn_tune(sdnn_net net, int64_t rows, void* stream) {
+sdnn_status sdnn_tune(sdnn_net net, const float* y_sample, int64_t rows, void* stream) {
     if (!net) return fail(SDNN_EINVAL, "net is NULL");
     TRY(host_error(net));
+    if (rows < 0) return fail(SDNN_EINVAL, "rows < 0");
+    if (y_sample && rows > net->d.max_rows)
+        return fail(SDNN_EINVAL, "rows = %lld exceeds max_rows = %lld", (long long)rows, (long long)net->d.max_rows);
     hipStream_t s = (hipStream_t)stream;
     const int N = net->d.n_neurons;
-    const int64_t rt = std::min<int64_t>(rows, net->d.max_rows / 2);
+    // the caller's rows (outputs into the workspace buffer), or all-ones rows in the
+    // first half of the workspace buffer and the outputs in its second half
+    const int64_t rt = y_sample ? rows : std::min<int64_t>(rows, net->d.max_rows / 2);
     if (rt < 1) return SDNN_OK;   // nothing to time with
-    float* in = net->act;
-    float* outb = net->act + (size_t)rt * N;
-    hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for(rt * N)), dim3(256), 0, s, in, rt * N, 1.0f);
-    HIPCHK(hipGetLastError());
+    const float* in = y_sample ? y_sample : net->act;
+    float* outb = y_sample ? net->act : net->act + (size_t)rt * N;
+    if (!y_sample) {
+        hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for(rt * N)), dim3(256), 0, s, net->act, rt * N, 1.0f);
+        HIPCHK(hipGetLastError());
+    }
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     float best = 1e30f;
     int best_v = net->variant, best_g = net->grid, best_cg = net->chain_grid;
+    // The kernel that matters is the one the forward runs: the persistent chain
+    // kernel (timed here over one layer: init, then the cooperative launch with its
+    // work list, liveness and grid barrier), or, for the graph and eager forms, the
+    // per-layer launch.
+    const bool chain = net->exec == SDNN_EXEC_PERSISTENT || net->exec == SDNN_EXEC_AUTO;
     // Variants of one family share the per-output arithmetic order (the scheduled
     // kernel sums slots in schedule order), so tuning never changes results.
     const bool fam_sched = var(net).staged == 2;
@@ -959,6 +971,46 @@ sdnn_status sdnn_tune(sdnn_net net, int64_t rows, void* stream) {
         if (!variant_fits(net, v) || (v.staged == 2) != fam_sched) continue;
         int g = 0, cg = 0;
         if (prepare_variant(net, vi, &g, &cg) != SDNN_OK) continue;
+        std::unique_ptr<Launch> init, run;
+        if (chain) {
+            // a one-layer chain: layer 0 reads `in` and writes `outb` (its output buffer)
+            ChainArgs c{};
+            c.y0 = in;
+            c.y_out = outb;
+            c.act = outb;
+            c.idx = net->idx;
+            c.w = net->w;
+            c.b = net->b;
+            c.list0 = net->list0;
+            c.list1 = net->list1;
+            c.cnt = net->cnt;
+            c.alive = net->alive;
+            c.bar = net->bar;
+            c.err = net->err;
+            c.rows = (int32_t)rt;
+            c.N = N;
+            c.L = 1;
+            c.ckpt_every = 2;
+            c.compaction = net->compaction ? 1 : 0;
+            c.clamp = net->d.clamp;
+            if (net->sched) {
+                c.ent = net->ent;
+                c.lane_neuron = net->lane_neuron;
+                c.wave_steps = net->wave_steps;
+                c.tile_bits = net->tile_bits;
+                c.prog = net->prog;
+                c.parts = net->parts;
+                c.nblk = net->nblk;
+            }
+            c.packed = net->packed;
+            c.wide_words = net->wide_words;
+            c.row_words = net->row_words;
+            c.row_parts = net->row_parts;
+            init = mk((const void*)&k_chain_init, dim3(1), dim3(256), 0, net->cnt, (int32_t)1, (int32_t)rt,
+                      (int32_t)c.compaction, net->bar, (int32_t)NBAR);
+            run = mk(v.chain_fn, dim3(cg), dim3(v.NT), fwd_lds_bytes(v, N), c);
+            run->cooperative = true;
+        }
         LayerArgs a{};
         a.yin = in;
         a.yout = outb;
@@ -970,10 +1022,23 @@ sdnn_status sdnn_tune(sdnn_net net, int64_t rows, void* stream) {
         a.clamp = net->d.clamp;
         fill_sched(net, a, 0);
         const int gg = v.staged >= 2 ? g : std::max(1, std::min<int>(g, (int)((rt + v.T - 1) / v.T)));
-        HIPCHK(launch_layer(net, v, gg, a, rt, s));
+        auto once = [&]() -> sdnn_status {
+            if (!chain) {
+                HIPCHK(launch_layer(net, v, gg, a, rt, s));
+                return SDNN_OK;
+            }
+            Plan p;
+            p.push_back(std::move(init));
+            p.push_back(std::move(run));
+            const sdnn_status st = issue(p, s);
+            init = std::move(p[0]);
+            run = std::move(p[1]);
+            return st;
+        };
+        TRY(once());
         HIPCHK(hipEventRecord(e0, s));
         const int reps = 3;
-        for (int r = 0; r < reps; ++r) HIPCHK(launch_layer(net, v, gg, a, rt, s));
+        for (int r = 0; r < reps; ++r) TRY(once());
         HIPCHK(hipEventRecord(e1, s));
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0.f;

@@ -50,7 +50,7 @@ PROTOTYPES = [
     ("sdnn_set_plan", _I32, [_P, ctypes.POINTER(sdnn_plan)]),
     ("sdnn_set_timing", _I32, [_P, _I32]),
     ("sdnn_kernel_time", _I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I32)]),
-    ("sdnn_tune", _I32, [_P, _I64, _P]),
+    ("sdnn_tune", _I32, [_P, _P, _I64, _P]),
     ("sdnn_forward", _I32, [_P, _P, _I64, _P, _I32, _P, _P, _P, _P, _P, _P]),
     ("sdnn_layer", _I32, [_P, _I32, _P, _I64, _P, _P]),
     ("sdnn_backward", _I32, [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
@@ -158,8 +158,8 @@ def sdnn_set_plan(h, rows_per_tile: int, threads: int, variant: int) -> None:
     _chk(lib().sdnn_set_plan(h, ctypes.byref(p)), "sdnn_set_plan")
 
 
-def sdnn_tune(h, rows: int, stream=None) -> None:
-    _chk(lib().sdnn_tune(h, rows, _stream(stream)), "sdnn_tune")
+def sdnn_tune(h, rows: int, y_sample=None, stream=None) -> None:
+    _chk(lib().sdnn_tune(h, _ptr(y_sample), rows, _stream(stream)), "sdnn_tune")
 
 
 def sdnn_forward(h, y0, rows, batch_off, n_batches, y_out, nz_rows, n_nz, ckpt=None, layer_rows=None,
@@ -265,8 +265,13 @@ class Net:
         sdnn_set_plan(self.h, rows_per_tile, threads, variant)
         return self.plan
 
-    def tune(self, rows: int, stream=None) -> dict:
-        sdnn_tune(self.h, rows, stream)
+    def tune(self, rows: int, y_sample: Optional[torch.Tensor] = None, stream=None) -> dict:
+        """Autotune the tile plan on `rows` rows: the first rows of y_sample (the
+        workload's activations) when given, else all-ones rows."""
+        if y_sample is not None:
+            rows = min(rows, y_sample.shape[0])
+            y_sample = y_sample[:rows].contiguous()
+        sdnn_tune(self.h, rows, y_sample, stream)
         return self.plan
 
     def ckpt_numel(self, rows: int) -> int:

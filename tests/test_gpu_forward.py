@@ -214,6 +214,12 @@ def test_autotune_keeps_results(P):
     assert plan["tuned_us"] > 0
     c, _ = run_forward(net, y0, mode="graph")
     assert torch.equal(a["y"], c["y"])
+    plan = net.tune(600, y_sample=y0)                  # on the workload's own rows
+    assert plan["tuned_us"] > 0
+    c, _ = run_forward(net, y0, mode="graph")
+    assert torch.equal(a["y"], c["y"])
+    with pytest.raises(P.SdnnError, match="EINVAL"):
+        P.sdnn.sdnn_tune(net.h, 601, torch.zeros(601, 1024, device=DEV))
 
 
 @pytest.mark.slow

@@ -98,3 +98,23 @@ def test_row_empty_and_single_row(P):
             else:
                 assert len(nz) == 0
     net.close()
+
+
+def test_row_family_autotune_on_the_workload(P):
+    """At 16384 neurons the tuner chooses among the one-row-tile, LDS-staged and
+    wide-layer kernels, which sum in the same order: timing them on the workload's
+    rows picks a plan and leaves every output bitwise unchanged."""
+    N, rows = 16384, 600
+    cfg = gen.CONFIGS["S3"].with_(n_neurons=N, n_layers=3, rows=rows, seed=29)
+    idx, w, b = upload(cfg)
+    y0 = torch.from_numpy(gen.make_inputs(cfg)).to(DEV)
+    net = P.Net(idx, w, b, max_rows=rows)
+    a = net.forward(y0, batch_off=[0, 250, rows])
+    torch.cuda.synchronize()
+    plan = net.tune(rows, y_sample=y0)
+    print("tuned plan", plan, flush=True)
+    assert plan["tuned_us"] > 0
+    c = net.forward(y0, batch_off=[0, 250, rows])
+    torch.cuda.synchronize()
+    assert torch.equal(a["y"], c["y"])
+    net.close()
