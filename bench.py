@@ -67,6 +67,9 @@ def parse():
                     help="also time the forward with parameters streamed from host memory")
     ap.add_argument("--table", default="", metavar="CONFIGS",
                     help="also run the per-config results table (e.g. C1,C2,C3,C4,C5,S2,S3)")
+    ap.add_argument("--plain", dest="plain", action="store_true", default=True,
+                    help="also time the plain form (batches one after another) of a batched headline")
+    ap.add_argument("--no-plain", dest="plain", action="store_false")
     ap.add_argument("--tune", action="store_true", default=True)
     ap.add_argument("--no-tune", dest="tune", action="store_false")
     return ap.parse_args()
@@ -90,20 +93,27 @@ def forward_bytes(prof, N, L):
 
 # committed rocprofv3 counter summaries of the persistent chain kernels, per
 # headline workload: (summary, kernel source it was taken with)
-PROFILES = {"C4": ("k_chain_wide_C4_forward.md", "sdnn_fwd.hip"),
-            "C2": ("k_chain_sched_C2_forward.md", "sdnn_fwd.hip")}
+PROFILES = {"C4": "k_chain_wide_C4_forward.md", "C2": "k_chain_sched_C2_forward.md"}
+# the sources the forward kernels are built from (hashed together)
+KERNEL_SOURCES = ("sdnn_fwd.hip", "sdnn_device.hpp", "sdnn_internal.hpp")
+
+
+def kernel_source_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for src in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2004_10908_amd", "csrc", src), "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(workload, kernel):
     """HBM bytes per launch of the persistent chain kernel from its committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the summary is for another
     kernel or the kernel source has changed since those counters were taken."""
-    import hashlib
     if workload not in PROFILES:
         return None
-    summary, src = PROFILES[workload]
     try:
-        text = open(os.path.join(ROOT, "profiles", summary)).read()
+        text = open(os.path.join(ROOT, "profiles", PROFILES[workload])).read()
     except OSError:
         return None
     vals = {}
@@ -111,10 +121,7 @@ def measured_traffic(workload, kernel):
         k, _, v = line.strip().partition(": ")
         if k in ("traffic_bytes_per_launch", "kernel_source_sha256", "kernel"):
             vals[k] = v.strip()
-    if len(vals) != 3 or vals["kernel"] != kernel:
-        return None
-    path = os.path.join(ROOT, "paper_2004_10908_amd", "csrc", src)
-    if hashlib.sha256(open(path, "rb").read()).hexdigest() != vals["kernel_source_sha256"]:
+    if len(vals) != 3 or vals["kernel"] != kernel or kernel_source_sha256() != vals["kernel_source_sha256"]:
         return None
     return int(vals["traffic_bytes_per_launch"])
 
@@ -258,7 +265,7 @@ def main():
     extras.update({"engines_ms": {k: round(v, 4) for k, v in engines.items()}, "plan": plan,
                    "profile_head": prof[:6].tolist(), "live_edges_per_s": live_edges(prof, N, L) / (ms / 1e3),
                    "alg_bytes": alg})
-    if batched:
+    if batched and args.plain:
         # the plain form of the same workload: the batches one after another through
         # the layer graph
         net.set_exec("graph")
@@ -305,6 +312,9 @@ def main():
                        "parallelism": "single-gpu", "engine": engine},
             "roofline": roofline, "cpu_baseline": cpu, "extras": extras}
     print(json.dumps(line), flush=True)
+    # every GPU call is done: unload the library now rather than at interpreter exit
+    torch.cuda.synchronize()
+    P.sdnn.unload()
 
 
 def full_live_layer(torch, net, y, reps=10):

@@ -90,7 +90,9 @@ typedef struct {
     int32_t grid;            /* workgroups per layer launch (grid-stride over tiles) */
     int32_t variant;         /* 2 = scheduled resident-weight kernel, 0 = LDS-staged rows,
                                 4 = one-row tiles with resident weights (forward-only nets of
-                                    2048 < N <= 16384 neurons, N % 4 == 0),
+                                    2048 < N <= 16384 neurons, N % 4 == 0), ascending slot order,
+                                5 = the same with each neuron's slots in a create-time order
+                                    that spreads a half-wave's LDS reads over distinct banks,
                                 1 = direct gather (rows too wide for LDS),
                                 3 = wide layers: rows packed T per tile [N][T] in the workspace,
                                     one T*4-byte gather per slot (forward-only nets whose
@@ -258,6 +260,22 @@ sdnn_status sdnn_mse_noalloc(const float *y, const float *t, int64_t n, float *d
  */
 int32_t sdnn_schedule_host(const int32_t *idx, int32_t n_neurons, int32_t n_layers, int32_t dmax, uint32_t *ent,
                            int32_t *lane_neuron, int32_t *steps);
+
+/*
+ * Host-side slot orders of the bank-scheduled one-row-tile kernel (plan variant 5),
+ * as sdnn_create builds them (no GPU involved).  The kernel reads an activation row
+ * from LDS with 4-byte reads, one slot per lane per step; a half-wave of 32 lanes
+ * (32 consecutive neurons) is served in one pass when its lanes hit 32 distinct
+ * banks (input id mod 32).  For every such block the orders take K "double" steps
+ * (each bank at most two lanes) and 32 - K conflict-free steps, with K = max(max_b
+ * d_b - 32, 32 - min_b d_b) for the block's per-bank slot counts d_b (a greedy
+ * order for a partial last block).
+ *   idx   host int32 [L][N][k], ids in [0, N)
+ *   perm  host uint8 [L][N][k]: perm[l][j][step] = the slot neuron j reads at step
+ * Returns the summed cost in LDS passes over all blocks (sum over steps of the
+ * busiest bank's lane count), or SDNN_EINVAL (< 0) for bad arguments.
+ */
+int64_t sdnn_row_schedule_host(const int32_t *idx, int32_t n_neurons, int32_t n_layers, uint8_t *perm);
 
 /* Synchronize `stream` and report whether a kernel of this net raised its error word.
  * The word stays set: after SDNN_EDEVICE the net's scratch state (work lists, per-tile

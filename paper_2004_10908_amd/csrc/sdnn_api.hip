@@ -66,8 +66,8 @@ struct Layout {
     bool sched = false;
     bool wide = false;
     size_t packed = 0, wide_words = 0;
-    bool row = false;
-    size_t row_words = 0;
+    bool row = false, row_sched = false;
+    size_t row_words = 0, row_perm = 0;
     size_t tr_ptr = 0, tr_e = 0, seg = 0, gbuf0 = 0, gbuf1 = 0, pdw = 0, pdb = 0;
     size_t total = 0;
 };
@@ -141,6 +141,9 @@ Layout make_layout(const sdnn_desc& d) {
     }
     y.row = row_possible(d);
     if (y.row) y.row_words = take(R * 4);
+    // the bank-scheduled slot order of every layer (32 bytes per neuron)
+    y.row_sched = y.row && !(d.flags & SDNN_NO_SCHEDULE);
+    if (y.row_sched) y.row_perm = take(L * N * K);
     y.bar = take(NBAR * 4);
     y.fin = take(FIN_BLOCKS * 4);
     y.err = take(64);
@@ -248,6 +251,7 @@ struct sdnn_net_s {
     bool row = false;                   // one-row-tile kernel available
     int32_t* row_words = nullptr;
     int row_parts = 0;
+    uint8_t* row_perm = nullptr;        // its bank-scheduled slot orders (null: ascending only)
     uint32_t* ent = nullptr;
     int32_t *lane_neuron = nullptr, *wave_steps = nullptr, *tile_bits = nullptr, *prog = nullptr;
     int parts = 1, nblk = 0;
@@ -287,6 +291,7 @@ sdnn_status host_error(const sdnn_net_s* n) {
 }
 
 bool variant_fits(const sdnn_net_s* n, const FwdVariant& v) {
+    if (v.staged == 5) return n->row && n->row_perm;
     if (v.staged == 4) return n->row;
     if (v.staged == 3) return n->wide;
     if (v.staged == 2) return n->sched;
@@ -300,6 +305,7 @@ void fill_sched(const sdnn_net_s* n, LayerArgs& a, int l) {
     a.wide_words = n->wide_words;
     a.row_words = n->row_words;
     a.row_parts = n->row_parts;
+    a.row_perm = n->row_perm ? n->row_perm + (size_t)l * n->d.n_neurons * K : nullptr;
     if (!n->sched) return;
     const size_t npad = (size_t)n->nblk * 64;
     a.ent = n->ent + (size_t)l * npad * SCHED_DSTORE;
@@ -336,7 +342,7 @@ sdnn_status prepare_variant(sdnn_net_s* n, int vi, int* grid, int* chain_grid) {
         *grid = SCHED_GRID;
         *chain_grid = SCHED_GRID;
     }
-    if (v.staged == 4) {
+    if (v.staged == 4 || v.staged == 5) {
         // one workgroup per CU, mapped to (XCD, part, stream) like the scheduled kernels
         if (*grid < ROW_GRID || *chain_grid < ROW_GRID)
             return fail(SDNN_EUNSUPPORTED, "one-row-tile kernel needs %d co-resident workgroups", ROW_GRID);
@@ -354,8 +360,11 @@ int default_variant(const sdnn_net_s* n) {
         for (int i = 0; i < fwd_variant_count(); ++i)
             if (fwd_variant(i).staged == 2) return i;
     if (n->row)
-        for (int i = 0; i < fwd_variant_count(); ++i)
-            if (fwd_variant(i).staged == 4) return i;
+        for (int want : {5, 4}) {
+            if (want == 5 && !n->row_perm) continue;
+            for (int i = 0; i < fwd_variant_count(); ++i)
+                if (fwd_variant(i).staged == want) return i;
+        }
     int best = -1, bestT = 0;
     for (int i = 0; i < fwd_variant_count(); ++i) {
         const FwdVariant& v = fwd_variant(i);
@@ -570,6 +579,7 @@ Plan plan_persistent(const sdnn_net_s* n, const float* y0, int64_t rows, float* 
     c.wide_words = n->wide_words;
     c.row_words = n->row_words;
     c.row_parts = n->row_parts;
+    c.row_perm = n->row_perm;
     auto ch = mk(v.chain_fn, dim3(n->chain_grid), dim3(v.NT), sh, c);
     ch->cooperative = true;
     ch->timed = true;
@@ -861,6 +871,22 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
             }
         }
     }
+    if (lay.row_sched) {
+        // bank-scheduled slot orders of the one-row-tile kernel, built on the host
+        // from a copy of the ids (ids outside [0, N) leave the ascending order only)
+        std::vector<int32_t> hidx((size_t)L * N * K);
+        HIPCHK(hipMemcpyAsync(hidx.data(), idx, hidx.size() * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        bool ids_ok = true;
+        for (size_t i = 0; i < hidx.size() && ids_ok; ++i) ids_ok = hidx[i] >= 0 && hidx[i] < N;
+        if (ids_ok) {
+            std::vector<uint8_t> perm((size_t)L * N * K);
+            build_row_schedule(hidx.data(), N, L, perm.data());
+            n->row_perm = (uint8_t*)(n->ws + lay.row_perm);
+            HIPCHK(hipMemcpyAsync(n->row_perm, perm.data(), perm.size(), hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+    }
     n->variant = default_variant(n.get());
     TRY(prepare_variant(n.get(), n->variant, &n->grid, &n->chain_grid));
     HIPCHK(hipStreamSynchronize(s));
@@ -964,11 +990,12 @@ sdnn_status sdnn_tune(sdnn_net net, const float* y_sample, int64_t rows, void* s
     // per-layer launch.
     const bool chain = net->exec == SDNN_EXEC_PERSISTENT || net->exec == SDNN_EXEC_AUTO;
     // Variants of one family share the per-output arithmetic order (the scheduled
-    // kernel sums slots in schedule order), so tuning never changes results.
-    const bool fam_sched = var(net).staged == 2;
+    // kernels sum slots in their create-time order), so tuning never changes results.
+    auto family = [](int staged) { return staged == 2 || staged == 5 ? staged : 0; };
+    const int fam = family(var(net).staged);
     for (int vi = 0; vi < fwd_variant_count(); ++vi) {
         const FwdVariant& v = fwd_variant(vi);
-        if (!variant_fits(net, v) || (v.staged == 2) != fam_sched) continue;
+        if (!variant_fits(net, v) || family(v.staged) != fam) continue;
         int g = 0, cg = 0;
         if (prepare_variant(net, vi, &g, &cg) != SDNN_OK) continue;
         std::unique_ptr<Launch> init, run;
@@ -1006,6 +1033,7 @@ sdnn_status sdnn_tune(sdnn_net net, const float* y_sample, int64_t rows, void* s
             c.wide_words = net->wide_words;
             c.row_words = net->row_words;
             c.row_parts = net->row_parts;
+            c.row_perm = net->row_perm;
             init = mk((const void*)&k_chain_init, dim3(1), dim3(256), 0, net->cnt, (int32_t)1, (int32_t)rt,
                       (int32_t)c.compaction, net->bar, (int32_t)NBAR);
             run = mk(v.chain_fn, dim3(cg), dim3(v.NT), fwd_lds_bytes(v, N), c);
@@ -1380,6 +1408,13 @@ sdnn_status sdnn_mse_noalloc(const float* y, const float* t, int64_t n, float* d
                            n ? 1.f / (float)n : 0.f);
     HIPCHK(hipGetLastError());
     return SDNN_OK;
+}
+
+int64_t sdnn_row_schedule_host(const int32_t* idx, int32_t n_neurons, int32_t n_layers, uint8_t* perm) {
+    if (!idx || !perm || n_neurons < K || n_layers < 1) return fail(SDNN_EINVAL, "bad arguments");
+    for (size_t i = 0; i < (size_t)n_layers * n_neurons * K; ++i)
+        if (idx[i] < 0 || idx[i] >= n_neurons) return fail(SDNN_EINVAL, "idx out of range");
+    return build_row_schedule(idx, n_neurons, n_layers, perm);
 }
 
 int32_t sdnn_schedule_host(const int32_t* idx, int32_t n_neurons, int32_t n_layers, int32_t dmax, uint32_t* ent,

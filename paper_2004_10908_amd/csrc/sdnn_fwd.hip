@@ -1476,6 +1476,7 @@ static const FwdVariant g_variants[] = {
     SDNN_VW(32, 256), SDNN_VW(32, 512),
     SDNN_VW(16, 1024), SDNN_VW(32, 1024),
     {1, ROW_NT, 4, (const void*)&k_layer_row, (const void*)&k_chain_row, nullptr},
+    {1, ROW_NT, 5, (const void*)&k_layer_row_sched, (const void*)&k_chain_row_sched, nullptr},
 };
 #undef SDNN_V
 #undef SDNN_VD

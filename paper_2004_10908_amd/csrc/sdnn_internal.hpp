@@ -55,6 +55,7 @@ struct LayerArgs {
     // parts with a nonzero output), zero between layers
     int32_t* row_words;
     int32_t row_parts;           // G: parts of ROW_PART neurons sharing a row
+    const uint8_t* row_perm;     // [N][K] slot order of this layer (bank-scheduled variant), or null
 };
 
 // Scheduled weight-gradient pass over one layer (rows are compact 0..R-1).
@@ -137,6 +138,7 @@ struct ChainArgs {
     // one-row-tile kernel only
     int32_t* row_words;
     int32_t row_parts;
+    const uint8_t* row_perm;     // [L][N][K] slot orders (bank-scheduled variant), or null
 };
 
 // Error codes written to the device error word.
@@ -146,7 +148,8 @@ enum DeviceError : int32_t { DEV_OK = 0, DEV_BARRIER_TIMEOUT = 1 };
 struct FwdVariant {
     int T;          // rows per tile
     int NT;         // threads per workgroup
-    int staged;     // 4 = one-row tiles (resident weights), 3 = wide (packed row tiles),
+    int staged;     // 5 = one-row tiles, bank-scheduled slot order; 4 = one-row tiles
+                    // (resident weights), ascending order; 3 = wide (packed row tiles),
                     // 2 = scheduled resident-weight kernel,
                     // 1 = rows staged in LDS, 0 = direct gather
     const void* layer_fn;    // __global__ void(LayerArgs)
@@ -171,11 +174,16 @@ constexpr size_t ROW_LDS = ROW_SCAL + 256;
 constexpr int ROW_GRID = 256;                            // one workgroup per CU, 8 XCDs x 32
 __global__ void k_layer_row(LayerArgs a);
 __global__ void k_chain_row(ChainArgs c);
+__global__ void k_layer_row_sched(LayerArgs a);
+__global__ void k_chain_row_sched(ChainArgs c);
+// slot orders of the bank-scheduled one-row-tile kernel (sdnn_rowsched.hip):
+// perm [L][N][K]; returns the summed cost in LDS passes
+int64_t build_row_schedule(const int32_t* idx, int N, int L, uint8_t* perm);
 
 int fwd_variant_count();
 const FwdVariant& fwd_variant(int i);
 inline size_t fwd_lds_bytes(const FwdVariant& v, int N) {
-    if (v.staged == 4) return ROW_LDS;
+    if (v.staged == 4 || v.staged == 5) return ROW_LDS;
     return v.staged == 2 ? sched_lds_bytes(N) : (v.staged == 1 ? (size_t)v.T * N * sizeof(float) : 0);
 }
 

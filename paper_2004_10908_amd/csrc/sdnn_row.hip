@@ -2,9 +2,10 @@
 //
 // The layer rule is the one of the other forward kernels (paper, section "Large
 // Sparse Neural Network Inference": y_{l+1}[r][j] = min(c, max(0, sum_k w[j][k]
-// y_l[r][idx[j][k]] + b[j]))), summed the same way: the 32 slots in ascending
-// order with fused multiply-adds, then the bias, so its outputs are bitwise equal
-// to the streamed-weight and wide-layer kernels.
+// y_l[r][idx[j][k]] + b[j]))), summed with fused multiply-adds, then the bias.  In
+// ascending slot order (plan variant 4) its outputs are bitwise equal to the
+// streamed-weight and wide-layer kernels; in the bank-scheduled order (variant 5)
+// each neuron's order is fixed at create time, so results are deterministic.
 //
 // Why this shape.  At N = 16384 a row of activations is 64 KB: two rows fit LDS
 // (160 KB) as a double buffer, four do not.  The other wide kernels read each
@@ -14,7 +15,9 @@
 //  * a workgroup of 1024 lanes owns a "part" of ROW_PART = 2048 consecutive
 //    neurons, two per lane; each lane keeps its neurons' 32 weights and 32 input
 //    offsets (16-bit LDS byte offsets, two per register) in registers, loaded once
-//    per layer;
+//    per layer, in ascending slot order or (plan variant 5) in the create-time
+//    order that keeps the 32 lanes of each half-wave on distinct LDS banks
+//    (sdnn_rowsched.hip); the sum runs in that order;
 //  * G = ceil(N / 2048) parts share each row ("tile" of one row).  Workgroup b
 //    serves part (b / 8) % G of tile stream ((b / 8) / G) * 8 + b % 8, so the G
 //    parts of a row run on one XCD (blockIdx % 8) and the row they all stage is
@@ -33,6 +36,7 @@
 // Dead rows are never written here: the finalize pass clears them where needed
 // (their alive flag says so), so no kernel writes its own input rows.
 #include <type_traits>
+#include <utility>
 
 #include "sdnn_internal.hpp"
 #include "sdnn_device.hpp"
@@ -98,9 +102,28 @@ struct RowNeuron {
     int j;      // neuron id, -1 past N
 };
 
+// With a slot order (PERM), step s reads slot row_perm[j][s] (the create-time
+// bank schedule); without one, step s reads slot s (ascending ids).
+template <bool PERM>
 __device__ __forceinline__ void row_load(const LayerArgs& a, int j, RowNeuron& n) {
     n.j = j < a.N ? j : -1;
-    if (n.j >= 0) {
+    if (PERM && n.j >= 0) {
+        const uint4* pp = reinterpret_cast<const uint4*>(a.row_perm + (size_t)j * K);
+        const uint4 p0 = pp[0], p1 = pp[1];
+        const uint32_t pw[8] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
+        const int32_t* ip = a.idx + (size_t)j * K;
+        const float* wp = a.w + (size_t)j * K;
+        uint32_t off[K];
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            const int slot = (int)((pw[s >> 2] >> (8 * (s & 3))) & 31u);
+            n.w[s] = wp[slot];
+            off[s] = (uint32_t)ip[slot] << 2;
+        }
+#pragma unroll
+        for (int q = 0; q < K / 2; ++q) n.o[q] = off[2 * q] | (off[2 * q + 1] << 16);
+        n.bj = a.b[j];
+    } else if (n.j >= 0) {
         const int4* ip = reinterpret_cast<const int4*>(a.idx + (size_t)j * K);
         const float4* wp = reinterpret_cast<const float4*>(a.w + (size_t)j * K);
 #pragma unroll
@@ -131,55 +154,58 @@ __device__ __forceinline__ uint32_t row_addr(const RowNeuron& n, uint32_t buf) {
     return __builtin_amdgcn_perm(buf, n.o[S >> 1], (S & 1) ? 0x07060302u : 0x07060100u);
 }
 
-// Both neurons over all 32 slots of the row in buffer `buf`, four slots at a
-// time: the reads of group g + 1 are issued before the FMAs of group g, and an
-// empty asm with a memory clobber after each group keeps the compiler from
-// hoisting every read of the row to the top (which would hold 64 results in
-// registers).  hook(g) runs before group g (the next row's copies go there).
-template <typename Hook>
+// Both neurons over all 32 slots of the row in buffer `buf`, RS slots at a time:
+// the reads of group g + 1 are issued before the FMAs of group g, and an empty asm
+// with a memory clobber after each group keeps the compiler from hoisting every
+// read of the row to the top (which would hold 64 results in registers).
+// hook(g) runs before group g (the next row's copies go there).
+template <int RS, int G>
+__device__ __forceinline__ void row_reads(const RowNeuron& n0, const RowNeuron& n1, uint32_t buf,
+                                          float (&r)[2 * RS]) {
+#pragma unroll
+    for (int u = 0; u < RS; ++u) {
+        r[2 * u] = row_lds_read(__builtin_amdgcn_perm(buf, n0.o[(RS * G + u) >> 1],
+                                                      ((RS * G + u) & 1) ? 0x07060302u : 0x07060100u));
+        r[2 * u + 1] = row_lds_read(__builtin_amdgcn_perm(buf, n1.o[(RS * G + u) >> 1],
+                                                          ((RS * G + u) & 1) ? 0x07060302u : 0x07060100u));
+    }
+}
+
+template <int RS, int G>
+__device__ __forceinline__ void row_fmas(const RowNeuron& n0, const RowNeuron& n1, const float (&r)[2 * RS],
+                                         float& acc0, float& acc1) {
+#pragma unroll
+    for (int u = 0; u < RS; ++u) {
+        acc0 = fmaf(n0.w[RS * G + u], r[2 * u], acc0);
+        acc1 = fmaf(n1.w[RS * G + u], r[2 * u + 1], acc1);
+    }
+    __asm__ volatile("" : "+v"(acc0), "+v"(acc1) : : "memory");
+}
+
+template <int RS, int G, typename Hook>
+__device__ __forceinline__ void row_group(const RowNeuron& n0, const RowNeuron& n1, uint32_t buf, float& acc0,
+                                          float& acc1, float (&v)[2][2 * RS], Hook& hook) {
+    hook(G);
+    if constexpr (G + 1 < K / RS) row_reads<RS, G + 1>(n0, n1, buf, v[(G + 1) & 1]);
+    row_fmas<RS, G>(n0, n1, v[G & 1], acc0, acc1);
+    if constexpr (G + 1 < K / RS) row_group<RS, G + 1>(n0, n1, buf, acc0, acc1, v, hook);
+}
+
+// RS: slots per group.  Four (eight reads in flight per wave) is faster for the
+// per-layer launch (S3 merged graph 546 against 580 ms); the persistent chain,
+// whose layer loop keeps more registers live, spills at four and takes two.
+template <int RS, typename Hook>
 __device__ __forceinline__ void row_steps(const RowNeuron& n0, const RowNeuron& n1, uint32_t buf, float& acc0,
                                           float& acc1, Hook&& hook) {
-    float v[2][8];
-    auto reads = [&](auto gc, float (&r)[8]) {
-        constexpr int g = decltype(gc)::value;
-        r[0] = row_lds_read(row_addr<4 * g + 0>(n0, buf));
-        r[1] = row_lds_read(row_addr<4 * g + 0>(n1, buf));
-        r[2] = row_lds_read(row_addr<4 * g + 1>(n0, buf));
-        r[3] = row_lds_read(row_addr<4 * g + 1>(n1, buf));
-        r[4] = row_lds_read(row_addr<4 * g + 2>(n0, buf));
-        r[5] = row_lds_read(row_addr<4 * g + 2>(n1, buf));
-        r[6] = row_lds_read(row_addr<4 * g + 3>(n0, buf));
-        r[7] = row_lds_read(row_addr<4 * g + 3>(n1, buf));
-    };
-    auto fmas = [&](auto gc, const float (&r)[8]) {
-        constexpr int g = decltype(gc)::value;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            acc0 = fmaf(n0.w[4 * g + u], r[2 * u], acc0);
-            acc1 = fmaf(n1.w[4 * g + u], r[2 * u + 1], acc1);
-        }
-        __asm__ volatile("" : "+v"(acc0), "+v"(acc1) : : "memory");
-    };
-    auto step = [&](auto gc) {
-        constexpr int g = decltype(gc)::value;
-        hook(g);
-        if constexpr (g + 1 < 8) reads(std::integral_constant<int, g + 1>{}, v[(g + 1) & 1]);
-        fmas(gc, v[g & 1]);
-    };
-    reads(std::integral_constant<int, 0>{}, v[0]);
-    step(std::integral_constant<int, 0>{});
-    step(std::integral_constant<int, 1>{});
-    step(std::integral_constant<int, 2>{});
-    step(std::integral_constant<int, 3>{});
-    step(std::integral_constant<int, 4>{});
-    step(std::integral_constant<int, 5>{});
-    step(std::integral_constant<int, 6>{});
-    step(std::integral_constant<int, 7>{});
+    float v[2][2 * RS];
+    row_reads<RS, 0>(n0, n1, buf, v[0]);
+    row_group<RS, 0>(n0, n1, buf, acc0, acc1, v, hook);
 }
 
 }  // namespace
 
 // One layer over the R rows of the work list (see the comment at the top).
+template <bool PERM, int RS>
 __device__ __forceinline__ void run_layer_row(const LayerArgs& a, int R) {
     const int N = a.N;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -202,8 +228,8 @@ __device__ __forceinline__ void run_layer_row(const LayerArgs& a, int R) {
     const lds_ptr<float> stage = lds_at<float>(ROW_STAGE);   // [2][ROW_PART]
 
     RowNeuron n0, n1;
-    row_load(a, pbase + wave * 64 + lane, n0);
-    row_load(a, pbase + WAVES * 64 + wave * 64 + lane, n1);
+    row_load<PERM>(a, pbase + wave * 64 + lane, n0);
+    row_load<PERM>(a, pbase + WAVES * 64 + wave * 64 + lane, n1);
 #pragma unroll
     for (int s = 0; s < K; ++s) __asm__ volatile("" : "+v"(n0.w[s]), "+v"(n1.w[s]));   // keep resident
 #pragma unroll
@@ -302,9 +328,9 @@ __device__ __forceinline__ void run_layer_row(const LayerArgs& a, int R) {
         auto hook = [&](int g) {
             if (more && g < mycopies) copy(row_n, buf ^ ROW_BUF_BYTES, g);
         };
-        row_steps(n0, n1, buf, acc0, acc1, hook);
+        row_steps<RS>(n0, n1, buf, acc0, acc1, hook);
         if (more)
-            for (int k = 8; k < mycopies; ++k) copy(row_n, buf ^ ROW_BUF_BYTES, k);
+            for (int k = K / RS; k < mycopies; ++k) copy(row_n, buf ^ ROW_BUF_BYTES, k);
         const float y0 = fminf(fmaxf(acc0 + n0.bj, 0.f), a.clamp);
         const float y1 = fminf(fmaxf(acc1 + n1.bj, 0.f), a.clamp);
         const lds_ptr<float> st = stage + (i & 1) * ROW_PART;
@@ -331,12 +357,8 @@ __device__ __forceinline__ void run_layer_row(const LayerArgs& a, int R) {
     __syncthreads();                                   // the LDS is reused by the next layer
 }
 
-__global__ __launch_bounds__(ROW_NT) void k_layer_row(LayerArgs a) {
-    const int R = a.cnt_in ? *a.cnt_in : a.nrows;
-    run_layer_row(a, R);
-}
-
-__global__ __launch_bounds__(ROW_NT) void k_chain_row(ChainArgs c) {
+template <bool PERM>
+__device__ __forceinline__ void chain_row(const ChainArgs& c) {
     int* s_ok = (int*)lds_at<int>(ROW_S_OK);
     unsigned gen = 0u;
     for (int l = 0; l < c.L; ++l) {
@@ -345,9 +367,19 @@ __global__ __launch_bounds__(ROW_NT) void k_chain_row(ChainArgs c) {
         LayerArgs a = chain_layer_args(c, l, R);
         a.row_parts = c.row_parts;
         a.row_words = c.row_words;
-        run_layer_row(a, R);
+        a.row_perm = c.row_perm ? c.row_perm + (size_t)l * c.N * K : nullptr;
+        run_layer_row<PERM, 2>(a, R);
         if (!grid_barrier(c.bar, gen, c.err, s_ok)) return;
     }
 }
+
+__global__ __launch_bounds__(ROW_NT) void k_layer_row(LayerArgs a) {
+    run_layer_row<false, 4>(a, a.cnt_in ? *a.cnt_in : a.nrows);
+}
+__global__ __launch_bounds__(ROW_NT) void k_chain_row(ChainArgs c) { chain_row<false>(c); }
+__global__ __launch_bounds__(ROW_NT) void k_layer_row_sched(LayerArgs a) {
+    run_layer_row<true, 4>(a, a.cnt_in ? *a.cnt_in : a.nrows);
+}
+__global__ __launch_bounds__(ROW_NT) void k_chain_row_sched(ChainArgs c) { chain_row<true>(c); }
 
 }  // namespace sdnn

@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 from typing import Optional, Sequence
 
 import torch
@@ -58,6 +59,7 @@ PROTOTYPES = [
     ("sdnn_mse", _I32, [_P, _P, _I64, _P, _P, _P]),
     ("sdnn_mse_noalloc", _I32, [_P, _P, _I64, _P, _P, _P]),
     ("sdnn_schedule_host", _I32, [_P, _I32, _I32, _I32, _P, _P, _P]),
+    ("sdnn_row_schedule_host", _I64, [_P, _I32, _I32, _P]),
     ("sdnn_check_device", _I32, [_P, _P]),
     ("sdnn_inject_device_error", _I32, [_P, _I32, _P]),
     ("sdnn_destroy", None, [_P]),
@@ -66,6 +68,7 @@ PROTOTYPES = [
 ]
 
 _lib: Optional[ctypes.CDLL] = None
+_live_nets = weakref.WeakSet()      # nets not yet closed (unload() closes them first)
 
 
 def lib() -> ctypes.CDLL:
@@ -81,6 +84,21 @@ def lib() -> ctypes.CDLL:
             fn.argtypes = args
         _lib = L
     return _lib
+
+
+def unload() -> None:
+    """Close every open net and unload libsdnn.so (dlclose), so that its HIP code
+    objects are unregistered now, while the HIP runtime (and a profiler attached to
+    the process) is still alive, instead of during interpreter exit.  The library
+    is loaded again by the next call that needs it."""
+    global _lib
+    for net in list(_live_nets):
+        net.close()
+    if _lib is not None:
+        import _ctypes
+        handle = _lib._handle
+        _lib = None
+        _ctypes.dlclose(handle)
 
 
 class SdnnError(RuntimeError):
@@ -193,6 +211,19 @@ def sdnn_mse_noalloc(y, t, n, dy=None, loss=None, stream=None) -> None:
     _chk(lib().sdnn_mse_noalloc(_ptr(y), _ptr(t), n, _ptr(dy), _ptr(loss), _stream(stream)), "sdnn_mse_noalloc")
 
 
+def sdnn_row_schedule_host(idx):
+    """Bank-scheduled slot orders of the one-row-tile kernel for an int32 numpy array
+    idx [L][N][k] -> (cost in LDS passes, perm uint8 [L][N][k])."""
+    import numpy as np
+    idx = np.ascontiguousarray(idx, np.int32)
+    L, N, _ = idx.shape
+    perm = np.zeros(idx.shape, np.uint8)
+    cost = lib().sdnn_row_schedule_host(idx.ctypes.data_as(_P), N, L, perm.ctypes.data_as(_P))
+    if cost < 0:
+        raise SdnnError(int(cost), "sdnn_row_schedule_host")
+    return int(cost), perm
+
+
 def sdnn_schedule_host(idx, dmax: int = 44):
     """Host slot schedule for an int32 numpy array idx [L][N][k] -> (worst, ent, lane_neuron, steps)."""
     import numpy as np
@@ -246,6 +277,7 @@ class Net:
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=idx.device)
         self.h = None
         self.h = sdnn_create(self.desc, self.idx, self.w, self.bias, self.workspace, self.ws_bytes, stream)
+        _live_nets.add(self)
         self.set_exec(exec_mode)
 
     def set_exec(self, mode) -> None:

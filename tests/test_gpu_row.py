@@ -1,8 +1,9 @@
-"""One-row-tile resident-weight kernel (plan variant 4, 2048 < N <= 16384): every
+"""One-row-tile resident-weight kernel (2048 < N <= 16384; plan variant 5 with the
+bank-scheduled slot order, the default, and variant 4 in ascending order): every
 layer of its chain checked element by element against the oracle through the
 chain's own activations, with several rows per tile stream, partial parts and
-partial row copies; bitwise equal to the LDS-staged kernel, which sums in the same
-order; dead rows cleared; the engines equal to each other."""
+partial row copies; variant 4 bitwise equal to the LDS-staged kernel, which sums
+in the same order; dead rows cleared; the engines equal to each other."""
 import numpy as np
 import pytest
 import torch
@@ -36,22 +37,24 @@ def test_row_chain_layer_sync(P, N, layers, rows, cfgname):
     y0h = gen.make_inputs(cfg)
     y0 = torch.from_numpy(y0h).to(DEV)
     net = P.Net(idx, w, b, max_rows=rows, ckpt_every=1)
-    assert net.plan["variant"] == 4, net.plan        # the default for these widths
+    assert net.plan["variant"] == 5, net.plan        # the default for these widths
     off = [0, rows // 5, rows // 5, rows // 5 + 1, rows]
-    base = None
-    for m in ("persistent", "graph", "graph_merged", "eager"):
-        o, nz, ys = forward_layers(net, y0, batch_off=off, mode=m)
-        if base is None:
-            prof = o["layer_rows"].cpu().numpy()
-            print(f"N={N} rows={rows} profile {prof.tolist()}", flush=True)
-            check_chain(lay, cfg.clamp, ys, prof, nz, y0h)
-            dead = np.setdiff1d(np.arange(rows), nz)
-            assert (o["y"].cpu().numpy()[dead] == 0).all(), "dead rows must be exactly zero"
-            base = (o["y"].clone(), ys)
-        else:
-            assert torch.equal(o["y"], base[0]), m
-            assert all(np.array_equal(a, c) for a, c in zip(ys, base[1])), m
-    # the LDS-staged streamed-weight kernel sums in the same order: bitwise equal
+    for plan in ((1, 1024, 5), (1, 1024, 4)):
+        net.set_plan(*plan)
+        base = None
+        for m in ("persistent", "graph", "graph_merged", "eager"):
+            o, nz, ys = forward_layers(net, y0, batch_off=off, mode=m)
+            if base is None:
+                prof = o["layer_rows"].cpu().numpy()
+                print(f"plan {plan} N={N} rows={rows} profile {prof.tolist()}", flush=True)
+                check_chain(lay, cfg.clamp, ys, prof, nz, y0h)
+                dead = np.setdiff1d(np.arange(rows), nz)
+                assert (o["y"].cpu().numpy()[dead] == 0).all(), "dead rows must be exactly zero"
+                base = (o["y"].clone(), ys)
+            else:
+                assert torch.equal(o["y"], base[0]), (plan, m)
+                assert all(np.array_equal(a, c) for a, c in zip(ys, base[1])), (plan, m)
+    # the LDS-staged streamed-weight kernel sums in ascending order like variant 4: bitwise equal
     net.set_plan(2, 1024, 0)
     o, nz, ys = forward_layers(net, y0, batch_off=off, mode="graph")
     assert torch.equal(o["y"], base[0])
@@ -67,7 +70,7 @@ def test_row_layer_sync_clamp_positive_bias_and_no_compaction(P):
     lay = host_layers(idx, w, b)
     y0h = gen.make_inputs(cfg)
     net = P.Net(idx, w, b, max_rows=rows, clamp=clamp)
-    assert net.plan["variant"] == 4, net.plan
+    assert net.plan["variant"] == 5, net.plan
     y = torch.from_numpy(y0h).to(DEV) * 1.5
     for l in range(layers):
         yn = net.layer(l, y)
@@ -101,20 +104,25 @@ def test_row_empty_and_single_row(P):
 
 
 def test_row_family_autotune_on_the_workload(P):
-    """At 16384 neurons the tuner chooses among the one-row-tile, LDS-staged and
-    wide-layer kernels, which sum in the same order: timing them on the workload's
-    rows picks a plan and leaves every output bitwise unchanged."""
+    """At 16384 neurons the tuner chooses within a family of kernels that sum in the
+    same order: the one-row-tile kernel in ascending order, the LDS-staged and the
+    wide-layer kernels (or the bank-scheduled one-row-tile kernel alone).  Timing
+    them on the workload's rows picks a plan and leaves every output bitwise
+    unchanged."""
     N, rows = 16384, 600
     cfg = gen.CONFIGS["S3"].with_(n_neurons=N, n_layers=3, rows=rows, seed=29)
     idx, w, b = upload(cfg)
     y0 = torch.from_numpy(gen.make_inputs(cfg)).to(DEV)
     net = P.Net(idx, w, b, max_rows=rows)
-    a = net.forward(y0, batch_off=[0, 250, rows])
-    torch.cuda.synchronize()
-    plan = net.tune(rows, y_sample=y0)
-    print("tuned plan", plan, flush=True)
-    assert plan["tuned_us"] > 0
-    c = net.forward(y0, batch_off=[0, 250, rows])
-    torch.cuda.synchronize()
-    assert torch.equal(a["y"], c["y"])
+    for plan0 in ((1, 1024, 5), (1, 1024, 4)):
+        net.set_plan(*plan0)
+        a = net.forward(y0, batch_off=[0, 250, rows])
+        torch.cuda.synchronize()
+        plan = net.tune(rows, y_sample=y0)
+        print("tuned plan", plan0, "->", plan, flush=True)
+        assert plan["tuned_us"] > 0
+        assert (plan["variant"] == 5) == (plan0[2] == 5)
+        c = net.forward(y0, batch_off=[0, 250, rows])
+        torch.cuda.synchronize()
+        assert torch.equal(a["y"], c["y"])
     net.close()

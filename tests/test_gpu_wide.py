@@ -38,7 +38,7 @@ def test_wide_forward_matches_oracle(P, N, layers, rows):
     if N > 16384:
         assert net.plan["variant"] == 3, net.plan    # a row exceeds one 64 KB LDS buffer: the wide kernel
     else:
-        assert net.plan["variant"] == 4, net.plan    # one-row tiles with resident weights
+        assert net.plan["variant"] == 5, net.plan    # one-row tiles with resident weights
         net.set_plan(32, 1024, 3)
     base = None
     for m in MODES:
@@ -103,7 +103,7 @@ def test_wide_variants_bitwise_equal(P):
     net.close()
 
 
-@pytest.mark.parametrize("T,NT,v", WIDE + [(1, 1024, 4)])
+@pytest.mark.parametrize("T,NT,v", WIDE + [(1, 1024, 4), (1, 1024, 5)])
 def test_wide_layer_sync_clamp_and_positive_bias(P, T, NT, v):
     """Layer by layer with a clamp the sums reach and a positive bias (compaction
     off), then the whole forward in every mode."""

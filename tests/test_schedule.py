@@ -63,3 +63,48 @@ def test_schedule_rejects_bad_ids(P):
     idx[0, 0, 0] = 64
     with pytest.raises(P.SdnnError):
         P.sdnn_schedule_host(idx)
+
+
+def _row_cost(idx, perm):
+    """LDS passes of the one-row-tile kernel's reads, recomputed from the orders: per
+    half-wave block of 32 consecutive neurons and step, the busiest bank's lane count
+    (bank = input id mod 32)."""
+    L, N, K = idx.shape
+    order = np.take_along_axis(idx, perm.astype(np.int64), axis=2) % 32      # [L][N][step] banks
+    cost = 0
+    for l in range(L):
+        for j0 in range(0, N, 32):
+            blk = order[l, j0:j0 + 32]
+            for s in range(K):
+                cost += np.bincount(blk[:, s], minlength=32).max()
+    return cost
+
+
+@pytest.mark.parametrize("N,L,seed", [(2048, 2, 5), (2052, 1, 6), (4100, 1, 7)])
+def test_row_schedule_orders(P, N, L, seed):
+    """Bank-scheduled slot orders: each neuron reads each of its slots exactly once; the
+    reported cost is the recomputed one; a full block costs at most 32 + K passes, K =
+    max(max_b d_b - 32, 32 - min_b d_b) of its per-bank slot counts (the construction's
+    bound), well under the ascending order's cost."""
+    cfg = gen.tiny_config(N, L, 1, seed)
+    idx = np.stack([gen.make_layer(cfg, l)[0] for l in range(L)])
+    cost, perm = P.sdnn.sdnn_row_schedule_host(idx)
+    assert (np.sort(perm, axis=2) == np.arange(32)).all(), "every slot exactly once per neuron"
+    assert cost == _row_cost(idx, perm)
+    ident = np.broadcast_to(np.arange(32, dtype=np.uint8), idx.shape)
+    ascending = _row_cost(idx, ident)
+    bound = 0
+    for l in range(L):
+        for j0 in range(0, N - N % 32, 32):
+            d = np.bincount((idx[l, j0:j0 + 32] % 32).ravel(), minlength=32)
+            bound += 32 + max(0, d.max() - 32, 32 - d.min())
+    full = _row_cost(idx[:, : N - N % 32], perm[:, : N - N % 32])
+    assert full <= bound
+    assert cost < 0.5 * ascending, (cost, ascending)
+
+
+def test_row_schedule_rejects_bad_ids(P):
+    idx = np.zeros((1, 64, 32), np.int32)
+    idx[0, 3, 7] = -1
+    with pytest.raises(P.SdnnError):
+        P.sdnn.sdnn_row_schedule_host(idx)
