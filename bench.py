@@ -65,6 +65,10 @@ def parse():
                     help="also time the stream/graph forms on these configs (C3,S2_20,C4)")
     ap.add_argument("--streamed", action="store_true", default=False,
                     help="also time the forward with parameters streamed from host memory")
+    ap.add_argument("--corun", default="", metavar="COUNTS",
+                    help="co-run throughput: run this many copies of the inference program at once "
+                         "(e.g. 1,2,4) and report weighted speedup")
+    ap.add_argument("--corun-args", default="", help="extra arguments for each co-running program")
     ap.add_argument("--table", default="", metavar="CONFIGS",
                     help="also run the per-config results table (e.g. C1,C2,C3,C4,C5,S2,S3)")
     ap.add_argument("--plain", dest="plain", action="store_true", default=True,
@@ -291,6 +295,8 @@ def main():
         extras["streamed"] = bench_streamed(args, torch, P, gen, dev)
     if args.table:
         extras["table"] = bench_table(args, torch, P, gen, dev)
+    if args.corun:
+        extras["corun"] = bench_corun(args)
 
     cpu = None
     if args.cpu:
@@ -631,6 +637,40 @@ def bench_table(args, torch, P, gen, dev):
         net.close()
         del idx, w, b, y0, o
         torch.cuda.empty_cache()
+    return res
+
+
+def bench_corun(args):
+    """The paper's co-run throughput experiment: K copies of the inference program
+    (paper_2004_10908_amd.corun: a batched forward of the whole input, then the
+    category check of every batch on the host) start together on this machine;
+    throughput = weighted speedup, the sum over copies of (time of the program
+    alone) / (its time in the co-run)."""
+    import subprocess
+    import tempfile
+    res = {}
+    alone = None
+    for k in [int(x) for x in args.corun.split(",")]:
+        go = os.path.join(tempfile.mkdtemp(prefix="corun"), "go")
+        cmd = [sys.executable, "-u", "-m", "paper_2004_10908_amd.corun", "--go", go] + args.corun_args.split()
+        procs = [subprocess.Popen(cmd, cwd=ROOT, stdout=subprocess.PIPE, text=True) for _ in range(k)]
+        for p in procs:
+            line = p.stdout.readline()
+            if line.strip() != "ready":
+                raise RuntimeError(f"co-run program did not start: {line!r}")
+        open(go, "w").close()
+        outs = []
+        for p in procs:
+            out, _ = p.communicate(timeout=600)
+            if p.returncode != 0:
+                raise RuntimeError(f"co-run program failed ({p.returncode})")
+            outs.append(json.loads(out.strip().splitlines()[-1]))
+        times = [sum(o["seconds"]) / len(o["seconds"]) for o in outs]
+        if alone is None:
+            alone = times[0]
+        res[str(k)] = {"seconds": [round(t, 4) for t in times], "weighted_speedup": round(sum(alone / t for t in times), 3),
+                       "mismatches": sum(o["mismatches"] for o in outs), "alive_rows": outs[0]["alive_rows"]}
+        log(f"corun {k}", res[str(k)])
     return res
 
 

@@ -9,8 +9,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_functions():
-    src = open(os.path.join(ROOT, "include", "sdnn.h")).read()
+def declared_functions(header="sdnn.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(sdnn_[a-z_]+)\s*\(", src)))
 
@@ -29,6 +29,12 @@ def test_library_exports_every_declared_symbol(L):
         assert hasattr(lib, n), n
     bound = {name for name, _, _ in L.sdnn.PROTOTYPES}
     assert set(names) == bound
+    from paper_2004_10908_amd import taskgraph
+    tg = declared_functions("sdnn_taskgraph.h")
+    assert len(tg) >= 7
+    for n in tg:
+        assert hasattr(lib, n), n
+    assert set(tg) == {name for name, _, _ in taskgraph.PROTOTYPES}
 
 
 def test_version_and_error_string(L):
