@@ -651,6 +651,7 @@ def bench_corun(args):
     res = {}
     alone = None
     for k in [int(x) for x in args.corun.split(",")]:
+        log(f"corun {k}: starting {k} program(s)")
         go = os.path.join(tempfile.mkdtemp(prefix="corun"), "go")
         cmd = [sys.executable, "-u", "-m", "paper_2004_10908_amd.corun", "--go", go] + args.corun_args.split()
         procs = [subprocess.Popen(cmd, cwd=ROOT, stdout=subprocess.PIPE, text=True) for _ in range(k)]
