@@ -100,11 +100,16 @@ typedef struct {
     float tuned_us;          /* measured time per full-live layer of the tuning shape (0 if untuned) */
 } sdnn_plan;
 
-/* Bytes of device workspace sdnn_create needs for this descriptor. */
+/* Bytes of device workspace sdnn_create needs for this descriptor.
+ * Paper: section "Large Sparse Neural Network Inference" (the net and the input
+ * batches live on the GPU; the paper streams them through 8 GB GPUs, here they are
+ * resident). */
 sdnn_status sdnn_workspace_size(const sdnn_desc *desc, size_t *bytes);
 
 /* Bytes of the checkpoint buffer a forward over `rows` rows must be given so that
- * sdnn_backward can run from it: (ceil(L / S) - 1) * rows * N * 4. */
+ * sdnn_backward can run from it: (ceil(L / S) - 1) * rows * N * 4.
+ * Paper: none (training is an extension of the layer rule of section "Large
+ * Sparse Neural Network Inference"). */
 sdnn_status sdnn_ckpt_size(const sdnn_desc *desc, int64_t rows, size_t *bytes);
 
 /*
@@ -117,14 +122,21 @@ sdnn_status sdnn_ckpt_size(const sdnn_desc *desc, int64_t rows, size_t *bytes);
  * If any bias is > 0, an all-zero row no longer stays all-zero, so compaction and
  * early exit are switched off for the whole net (results are unchanged).
  * Synchronizes `stream` (create is not a timed path).
+ * Paper: section "Large Sparse Neural Network Inference" (the problem's inputs:
+ * L sparse layer matrices and their biases) and section "Heterogeneous Tasking"
+ * (a GPU task graph is built once, then offloaded).
  */
 sdnn_status sdnn_create(const sdnn_desc *desc, const int32_t *idx, const float *w, const float *bias,
                         void *workspace, size_t ws_bytes, void *stream, sdnn_net *out);
 
-/* Choose how sdnn_forward runs the layer chain (SDNN_EXEC_*). */
+/* Choose how sdnn_forward runs the layer chain (SDNN_EXEC_*).
+ * Paper: section "Scheduling GPU Tasks" (one GPU task graph launched in one call)
+ * and the graph-construction comparison of section "Large Sparse Neural Network
+ * Inference". */
 sdnn_status sdnn_set_exec(sdnn_net net, int32_t mode);
 
-/* Read the current tile plan. */
+/* Read the current tile plan.  Paper: none (the GPU kernel's shape is left open
+ * in section "Large Sparse Neural Network Inference"). */
 sdnn_status sdnn_get_plan(sdnn_net net, sdnn_plan *plan);
 
 /* Select the kernel variant given by plan->rows_per_tile, plan->threads and
@@ -132,7 +144,7 @@ sdnn_status sdnn_get_plan(sdnn_net net, sdnn_plan *plan);
  * the variant's occupancy).  SDNN_EINVAL if no variant has those three values,
  * SDNN_EUNSUPPORTED if it does not fit this net (LDS, schedule, workspace).  Variants
  * of one family (0, 1 and 3; or 2) give bitwise-equal results.  Not thread-safe
- * against calls on the same net. */
+ * against calls on the same net.  Paper: none (as sdnn_get_plan). */
 sdnn_status sdnn_set_plan(sdnn_net net, const sdnn_plan *plan);
 
 /*
@@ -143,6 +155,7 @@ sdnn_status sdnn_set_plan(sdnn_net net, const sdnn_plan *plan);
  * time in milliseconds and the number of launches since the previous call (or
  * since timing was enabled), then starts a new sum.  Either output pointer may
  * be NULL.  Events are created on first use and released by sdnn_destroy.
+ * Paper: none (measurement support).
  */
 sdnn_status sdnn_set_timing(sdnn_net net, int32_t enable);
 sdnn_status sdnn_kernel_time(sdnn_net net, double *total_ms, int32_t *launches);
@@ -161,6 +174,9 @@ sdnn_status sdnn_tune(sdnn_net net, const float *y_sample, int64_t rows, void *s
 
 /*
  * Forward pass over `rows` input rows.
+ * Paper: section "Large Sparse Neural Network Inference" (the layered inference,
+ * its batches of inputs dispatched by a loop of condition tasks, section
+ * "Conditional Tasking", and the truth-category check of the result).
  *   y0        dev fp32 [rows][N]   input activations (not modified)
  *   batch_off host int64 [n_batches+1] ascending offsets, 0 .. rows, or NULL
  *             (one batch).  Batches are consecutive row ranges; rows are
@@ -186,6 +202,7 @@ sdnn_status sdnn_forward(sdnn_net net, const float *y0, int64_t rows, const int6
  * One layer over all `rows` rows, no compaction: y_out = min(c, max(0, y_in W_l + b_l)).
  * Used to check the forward layer by layer.  y_in/y_out dev fp32 [rows][N], must not overlap;
  * rows <= max_rows (the wide-layer kernels pack the rows into the workspace).
+ * Paper: section "Large Sparse Neural Network Inference" (one layer of the rule).
  */
 sdnn_status sdnn_layer(sdnn_net net, int32_t layer, const float *y_in, int64_t rows, float *y_out, void *stream);
 
@@ -200,6 +217,8 @@ sdnn_status sdnn_layer(sdnn_net net, int32_t layer, const float *y_in, int64_t r
  *   dbias     dev fp32 [L][N]      dL/db  (overwritten)
  *   dy0       dev fp32 [rows][N] or NULL: dL/dY_0 (overwritten)
  * Deterministic: no floating-point atomics; every sum has a fixed order.
+ * Paper: none (training is an extension of the layer rule of section "Large
+ * Sparse Neural Network Inference").
  */
 sdnn_status sdnn_backward(sdnn_net net, const float *y0, int64_t rows, const float *ckpt, const int32_t *nz_rows,
                           const int32_t *n_nz, const float *dy_out, float *dw, float *dbias, float *dy0,
@@ -213,6 +232,7 @@ sdnn_status sdnn_backward(sdnn_net net, const float *y0, int64_t rows, const flo
  *   y_in, y_out, dy_out dev fp32 [rows][N] (y_out = this layer's forward output);
  *   dw dev fp32 [N][k], dbias dev fp32 [N] (this layer's slices; overwritten);
  *   dy_in dev fp32 [rows][N] or NULL.  rows <= max_rows.
+ * Paper: none (as sdnn_backward).
  */
 sdnn_status sdnn_layer_backward(sdnn_net net, int32_t layer, const float *y_in, const float *y_out,
                                 const float *dy_out, int64_t rows, float *dw, float *dbias, float *dy_in,
@@ -223,6 +243,7 @@ sdnn_status sdnn_layer_backward(sdnn_net net, int32_t layer, const float *y_in, 
  *   dy (dev fp32 [n], may be NULL) = 2 (y - t) / n
  *   loss (dev fp32 [257], may be NULL): loss[0] = sum (y - t)^2 / n; loss[1..256]
  *   are scratch for per-block partial sums.  The loss is reduced in a fixed order.
+ * Paper: none (the training loss of the backward extension).
  */
 sdnn_status sdnn_mse(const float *y, const float *t, int64_t n, float *dy, float *loss, void *stream);
 
@@ -257,6 +278,7 @@ sdnn_status sdnn_mse_noalloc(const float *y, const float *t, int64_t n, float *d
  *   steps        host int32 [L][ceil(N / 64)]: steps of each block
  * Returns the largest block step count (> dmax: the schedule does not fit and the
  * entries past dmax were dropped), or SDNN_EINVAL / SDNN_EUNSUPPORTED.
+ * Paper: none (a kernel-design detail of this library).
  */
 int32_t sdnn_schedule_host(const int32_t *idx, int32_t n_neurons, int32_t n_layers, int32_t dmax, uint32_t *ent,
                            int32_t *lane_neuron, int32_t *steps);
@@ -274,6 +296,7 @@ int32_t sdnn_schedule_host(const int32_t *idx, int32_t n_neurons, int32_t n_laye
  *   perm  host uint8 [L][N][k]: perm[l][j][step] = the slot neuron j reads at step
  * Returns the summed cost in LDS passes over all blocks (sum over steps of the
  * busiest bank's lane count), or SDNN_EINVAL (< 0) for bad arguments.
+ * Paper: none (a kernel-design detail of this library).
  */
 int64_t sdnn_row_schedule_host(const int32_t *idx, int32_t n_neurons, int32_t n_layers, uint8_t *perm);
 
@@ -284,23 +307,23 @@ int64_t sdnn_row_schedule_host(const int32_t *idx, int32_t n_neurons, int32_t n_
  * error word into pinned host memory, and sdnn_forward, sdnn_layer, sdnn_backward,
  * sdnn_layer_backward and sdnn_tune return SDNN_EDEVICE (launching nothing) once that
  * copy has landed, i.e. on the first call that starts after the failing forward has
- * finished on the device. */
+ * finished on the device.  Paper: none (failure detection of this library). */
 sdnn_status sdnn_check_device(sdnn_net net, void *stream);
 
 /* Failure injection for tests of the error path: enqueue on `stream` a write of `code`
  * (nonzero) into the net's device error word, as a timed-out barrier would.  Every
  * persistent-kernel grid barrier then gives up at once (its kernel returns normally),
  * the next forward's finalize pass publishes the word, and the net must be recreated.
- * SDNN_EINVAL for a NULL net or code 0. */
+ * SDNN_EINVAL for a NULL net or code 0.  Paper: none (test support). */
 sdnn_status sdnn_inject_device_error(sdnn_net net, int32_t code, void *stream);
 
-/* Release the net (NULL-safe).  Does not free caller buffers. */
+/* Release the net (NULL-safe).  Does not free caller buffers.  Paper: none. */
 void sdnn_destroy(sdnn_net net);
 
-/* Thread-local message of the last failure. */
+/* Thread-local message of the last failure.  Paper: none. */
 const char *sdnn_last_error(void);
 
-/* Library version string. */
+/* Library version string.  Paper: none. */
 const char *sdnn_version(void);
 
 #ifdef __cplusplus

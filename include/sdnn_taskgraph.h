@@ -40,15 +40,18 @@ typedef struct sdnn_tg_graph_s *sdnn_tg_graph;
  * has finished on that stream.  SDNN_EINVAL for counts out of range, SDNN_EHIP if
  * a stream cannot be created.  GPU workers are currently switched off: n_gpu > 0
  * returns SDNN_EUNSUPPORTED (a process that ran GPU tasks on them ended with a
- * segmentation fault at exit, cause not yet found), so the pipeline cannot run. */
+ * segmentation fault at exit, cause not yet found), so the pipeline cannot run.
+ * Paper: section "Heterogeneous Work-stealing Architecture" (per-domain workers,
+ * per-worker queues per domain, a shared queue per domain). */
 int sdnn_tg_executor_create(int32_t n_cpu, int32_t n_gpu, sdnn_tg_executor *out);
 
 /* Stop the workers (after the graphs they run have finished) and release the
- * executor (NULL-safe). */
+ * executor (NULL-safe).  Paper: none. */
 void sdnn_tg_executor_destroy(sdnn_tg_executor ex);
 
 /* Counters since creation: stats4[0] tasks executed, [1] successful steals,
- * [2] failed steal attempts, [3] times a worker went to sleep. */
+ * [2] failed steal attempts, [3] times a worker went to sleep.  Paper: section
+ * "Heterogeneous Work-stealing Algorithm" (the quantities its analysis bounds). */
 int sdnn_tg_executor_stats(sdnn_tg_executor ex, int64_t *stats4);
 
 /* Self-checks of the scheduler (used by the tests): a layered DAG of `depth` levels
@@ -57,7 +60,9 @@ int sdnn_tg_executor_stats(sdnn_tg_executor ex, int64_t *stats4);
  * and a sink; *sum receives the sum of the values the tasks add (2 + sum over tasks
  * of level * width + index + 2).  And a loop: a body task followed by a condition
  * task that sends control back to the body until it has run `iterations` times
- * (at least once); *count receives the number of body runs. */
+ * (at least once); *count receives the number of body runs.  Paper: section
+ * "Task-level Scheduling Algorithm" (dependency counts; a condition task releases
+ * the one successor its return value names, section "Scheduling Condition Tasks"). */
 int sdnn_tg_run_diamond_chain(sdnn_tg_executor ex, int32_t width, int32_t depth, int32_t gpu_every, int64_t *sum);
 int sdnn_tg_run_condition_loop(sdnn_tg_executor ex, int32_t iterations, int32_t *count);
 
@@ -88,13 +93,15 @@ int sdnn_tg_run_condition_loop(sdnn_tg_executor ex, int32_t iterations, int32_t 
  * Allocates rows * N * 4 + (rows + n_batches) * 4 bytes of pinned host memory for
  * the run.  SDNN_EINVAL for bad arguments, SDNN_ENOMEM if the pinned buffers cannot
  * be allocated, SDNN_EDEVICE if a task failed (sdnn_tg_last_error names it).
+ * Paper: section "Large Sparse Neural Network Inference" (batches dispatched to the
+ * GPU, results checked by CPU tasks against the truth categories).
  */
 int sdnn_tg_pipeline_run(sdnn_tg_executor ex, sdnn_net *nets, int32_t n_nets, int32_t n_neurons, int64_t rows,
                          const int64_t *batch_off, int32_t n_batches, const int64_t *in_ptr, const int32_t *in_cols,
                          const int64_t *truth_off, const int32_t *truth_rows, float *y0_dev, float *y_dev,
                          int32_t *nz_dev, int32_t *n_nz_dev, int64_t *mismatches, double *seconds);
 
-/* Thread-local message of the last failure of a task-graph call. */
+/* Thread-local message of the last failure of a task-graph call.  Paper: none. */
 const char *sdnn_tg_last_error(void);
 
 #ifdef __cplusplus

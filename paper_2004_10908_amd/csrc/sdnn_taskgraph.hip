@@ -350,9 +350,12 @@ int sdnn_tg_executor_create(int32_t n_cpu, int32_t n_gpu, sdnn_tg_executor* out)
         return tg_fail(SDNN_EINVAL, "worker counts out of range (n_cpu 1..256, n_gpu 0..64)");
     // GPU-domain worker threads are switched off: a process that ran GPU tasks on
     // them (kernels launched from executor-owned threads) ended with a segmentation
-    // fault at exit after every task had finished, for a reason not yet found.
+    // fault at exit after every task had finished, for a reason not yet found.  Host
+    // builds against a stand-in HIP header (the sanitizer tests) keep them.
+#ifndef SDNN_TG_STANDIN_HIP
     if (n_gpu > 0)
         return tg_fail(SDNN_EUNSUPPORTED, "GPU-domain workers are switched off (n_gpu must be 0)");
+#endif
     auto ex = std::make_unique<sdnn_tg_executor_s>();
     for (int d = 0; d < NDOM; ++d) {
         ex->actives[d] = 0;
