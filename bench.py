@@ -46,11 +46,12 @@ K = 32
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--config", default="C4", choices=["C4", "C2"],
-                    help="headline workload: C4 (batched, 65536 x 1920) or C2 (plain, 4096 x 480)")
+    ap.add_argument("--config", default="C4", choices=["C4", "C2", "C3", "S2", "S3", "S4", "C1", "C5", "G5"],
+                    help="workload of the JSON line: C4 (batched, 65536 x 1920; the default) or another "
+                         "configuration (for profiling one kernel family)")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--engine", default="auto", choices=["auto", "graph", "persistent", "eager"],
+    ap.add_argument("--engine", default="auto", choices=["auto", "graph", "graph_merged", "persistent", "eager"],
                     help="auto: time graph and persistent in warm-up and keep the faster")
     ap.add_argument("--extras", dest="extras", action="store_true", default=True)
     ap.add_argument("--no-extras", dest="extras", action="store_false")
@@ -69,6 +70,8 @@ def parse():
                     help="co-run throughput: run this many copies of the inference program at once "
                          "(e.g. 1,2,4) and report weighted speedup")
     ap.add_argument("--corun-args", default="", help="extra arguments for each co-running program")
+    ap.add_argument("--table-forms", default="plain,merged,persistent",
+                    help="forms the results table times (a profiled run without cooperative launches: plain,merged)")
     ap.add_argument("--table", default="", metavar="CONFIGS",
                     help="also run the per-config results table (e.g. C1,C2,C3,C4,C5,S2,S3)")
     ap.add_argument("--plain", dest="plain", action="store_true", default=True,
@@ -604,13 +607,14 @@ def bench_table(args, torch, P, gen, dev):
              "alive_last": int(prof[L]), "alg_bytes": alg, "plan": net.plan}
         forms = [("plain", "graph")] + ([("merged", "graph_merged"), ("persistent", "persistent")] if off else
                                         [("persistent", "persistent")])
+        forms = [f for f in forms if f[0] in args.table_forms.split(",")]
         for form, eng in forms:
             net.set_exec(eng)
             ms = time_forward(torch, net, y0, o, steps, 1, batch_off=off)
             r[form] = {"ms": round(ms, 3), "nominal_edges_per_s": cfg.rows * cfg.nnz / (ms / 1e3),
                        "live_edges_per_s": live / (ms / 1e3), "alg_GBps": round(alg / ms / 1e6, 1),
                        "frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)}
-        if off:
+        if off and "merged" in r and "persistent" in r:
             best = min(("merged", "persistent"), key=lambda k: r[k]["ms"])
             r["batched_best"] = best
             r["batched_over_plain"] = round(r["plain"]["ms"] / r[best]["ms"], 3)
