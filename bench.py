@@ -102,7 +102,7 @@ def forward_bytes(prof, N, L):
 # headline workload: (summary, kernel source it was taken with)
 PROFILES = {"C4": "k_chain_wide_C4_forward.md", "C2": "k_chain_sched_C2_forward.md"}
 # the sources the forward kernels are built from (hashed together)
-KERNEL_SOURCES = ("sdnn_fwd.hip", "sdnn_device.hpp", "sdnn_internal.hpp")
+KERNEL_SOURCES = ("sdnn_fwd.hip", "sdnn_rowc.hip", "sdnn_device.hpp", "sdnn_internal.hpp")
 
 
 def kernel_source_sha256():
@@ -142,6 +142,10 @@ def chain_kernel_name(plan):
         return f"sdnn::k_chain_wide<{T}, {NT}>"
     if v == 4:
         return "sdnn::k_chain_row"
+    if v == 5:
+        return "sdnn::k_chain_row_sched"
+    if v == 6:
+        return f"sdnn::k_chain_rowc<{T}>"
     return f"sdnn::k_chain<{T}, {NT}, {'true' if v == 0 else 'false'}>"
 
 

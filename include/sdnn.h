@@ -93,6 +93,10 @@ typedef struct {
                                     2048 < N <= 16384 neurons, N % 4 == 0), ascending slot order,
                                 5 = the same with each neuron's slots in a create-time order
                                     that spreads a half-wave's LDS reads over distinct banks,
+                                6 = one-row tiles staged in rows_per_tile = 2 or 4 chunks,
+                                    resident weights of create-time neuron pairs (forward-only
+                                    nets of 16384 < N <= 65536 neurons, N % 2048 == 0),
+                                    ascending slot order,
                                 1 = direct gather (rows too wide for LDS),
                                 3 = wide layers: rows packed T per tile [N][T] in the workspace,
                                     one T*4-byte gather per slot (forward-only nets whose

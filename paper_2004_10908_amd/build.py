@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsdnn.so")
-SOURCES = ["sdnn_fwd.hip", "sdnn_row.hip", "sdnn_rowsched.hip", "sdnn_bwd.hip", "sdnn_sched.hip", "sdnn_taskgraph.hip", "sdnn_api.hip"]
+SOURCES = ["sdnn_fwd.hip", "sdnn_row.hip", "sdnn_rowc.hip", "sdnn_rowsched.hip", "sdnn_bwd.hip", "sdnn_sched.hip", "sdnn_taskgraph.hip", "sdnn_api.hip"]
 ARCH = os.environ.get("SDNN_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

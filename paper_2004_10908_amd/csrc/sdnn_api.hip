@@ -66,8 +66,8 @@ struct Layout {
     bool sched = false;
     bool wide = false;
     size_t packed = 0, wide_words = 0;
-    bool row = false, row_sched = false;
-    size_t row_words = 0, row_perm = 0;
+    bool row = false, row_sched = false, rowc = false;
+    size_t row_words = 0, row_perm = 0, rowc_img = 0, rowc_meta = 0, rowc_ovf = 0;
     size_t tr_ptr = 0, tr_e = 0, seg = 0, gbuf0 = 0, gbuf1 = 0, pdw = 0, pdb = 0;
     size_t total = 0;
 };
@@ -110,6 +110,15 @@ bool row_possible(const sdnn_desc& d) {
 }
 int row_parts(const sdnn_desc& d) { return (d.n_neurons + ROW_PART - 1) / ROW_PART; }
 
+// The chunked one-row-tile kernel: rows wider than one LDS buffer, staged in 2 or 4
+// chunks of at most 16384 ids; whole parts (N % 2048 == 0); a create-time pairing
+// of the neurons (so not with SDNN_NO_SCHEDULE, whose ids may change).
+bool rowc_possible(const sdnn_desc& d) {
+    return !trainable(d) && !(d.flags & SDNN_NO_SCHEDULE) && d.n_neurons % ROW_PART == 0 &&
+           d.n_neurons > ROW_NMAX && d.n_neurons <= ROWC_NMAX;
+}
+int rowc_chunks(const sdnn_desc& d) { return d.n_neurons <= 2 * ROW_NMAX ? 2 : 4; }
+
 Layout make_layout(const sdnn_desc& d) {
     Layout y;
     size_t off = 0;
@@ -140,7 +149,16 @@ Layout make_layout(const sdnn_desc& d) {
         y.wide_words = take(2 * ((R + WIDE_TMIN - 1) / WIDE_TMIN) * 4);
     }
     y.row = row_possible(d);
-    if (y.row) y.row_words = take(R * 4);
+    y.rowc = rowc_possible(d);
+    if (y.row || y.rowc) y.row_words = take(R * 4);
+    // the chunked kernel's lane images of every layer (register words, pair words,
+    // overflow lists): 400 bytes per pair of neurons and 16 KB per part
+    if (y.rowc) {
+        const size_t parts = N / ROW_PART;
+        y.rowc_img = take(L * parts * ROWC_IMG * ROW_NT * 4);
+        y.rowc_meta = take(L * parts * ROW_NT * 16);
+        y.rowc_ovf = take(L * parts * ROWC_OVF_CAP * 8);
+    }
     // the bank-scheduled slot order of every layer (32 bytes per neuron)
     y.row_sched = y.row && !(d.flags & SDNN_NO_SCHEDULE);
     if (y.row_sched) y.row_perm = take(L * N * K);
@@ -252,6 +270,9 @@ struct sdnn_net_s {
     int32_t* row_words = nullptr;
     int row_parts = 0;
     uint8_t* row_perm = nullptr;        // its bank-scheduled slot orders (null: ascending only)
+    bool rowc = false;                  // chunked one-row-tile kernel available (images built)
+    uint32_t *rowc_img = nullptr, *rowc_meta = nullptr, *rowc_ovf = nullptr;   // its lane images [L][...]
+    int rowc_chunks = 0;
     uint32_t* ent = nullptr;
     int32_t *lane_neuron = nullptr, *wave_steps = nullptr, *tile_bits = nullptr, *prog = nullptr;
     int parts = 1, nblk = 0;
@@ -291,6 +312,7 @@ sdnn_status host_error(const sdnn_net_s* n) {
 }
 
 bool variant_fits(const sdnn_net_s* n, const FwdVariant& v) {
+    if (v.staged == 6) return n->rowc && v.T == n->rowc_chunks;
     if (v.staged == 5) return n->row && n->row_perm;
     if (v.staged == 4) return n->row;
     if (v.staged == 3) return n->wide;
@@ -306,6 +328,12 @@ void fill_sched(const sdnn_net_s* n, LayerArgs& a, int l) {
     a.row_words = n->row_words;
     a.row_parts = n->row_parts;
     a.row_perm = n->row_perm ? n->row_perm + (size_t)l * n->d.n_neurons * K : nullptr;
+    if (n->rowc) {
+        const size_t parts = (size_t)n->row_parts;
+        a.rowc_img = n->rowc_img + (size_t)l * parts * ROWC_IMG * ROW_NT;
+        a.rowc_meta = n->rowc_meta + (size_t)l * parts * ROW_NT * 4;
+        a.rowc_ovf = n->rowc_ovf + (size_t)l * parts * ROWC_OVF_CAP * 2;
+    }
     if (!n->sched) return;
     const size_t npad = (size_t)n->nblk * 64;
     a.ent = n->ent + (size_t)l * npad * SCHED_DSTORE;
@@ -342,7 +370,7 @@ sdnn_status prepare_variant(sdnn_net_s* n, int vi, int* grid, int* chain_grid) {
         *grid = SCHED_GRID;
         *chain_grid = SCHED_GRID;
     }
-    if (v.staged == 4 || v.staged == 5) {
+    if (v.staged == 4 || v.staged == 5 || v.staged == 6) {
         // one workgroup per CU, mapped to (XCD, part, stream) like the scheduled kernels
         if (*grid < ROW_GRID || *chain_grid < ROW_GRID)
             return fail(SDNN_EUNSUPPORTED, "one-row-tile kernel needs %d co-resident workgroups", ROW_GRID);
@@ -365,6 +393,9 @@ int default_variant(const sdnn_net_s* n) {
             for (int i = 0; i < fwd_variant_count(); ++i)
                 if (fwd_variant(i).staged == want) return i;
         }
+    if (n->rowc)
+        for (int i = 0; i < fwd_variant_count(); ++i)
+            if (fwd_variant(i).staged == 6 && fwd_variant(i).T == n->rowc_chunks) return i;
     int best = -1, bestT = 0;
     for (int i = 0; i < fwd_variant_count(); ++i) {
         const FwdVariant& v = fwd_variant(i);
@@ -580,6 +611,9 @@ Plan plan_persistent(const sdnn_net_s* n, const float* y0, int64_t rows, float* 
     c.row_words = n->row_words;
     c.row_parts = n->row_parts;
     c.row_perm = n->row_perm;
+    c.rowc_img = n->rowc_img;
+    c.rowc_meta = n->rowc_meta;
+    c.rowc_ovf = n->rowc_ovf;
     auto ch = mk(v.chain_fn, dim3(n->chain_grid), dim3(v.NT), sh, c);
     ch->cooperative = true;
     ch->timed = true;
@@ -723,6 +757,10 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
         n->row_words = (int32_t*)(n->ws + lay.row_words);
         n->row_parts = row_parts(*desc);
     }
+    if (lay.rowc) {
+        n->row_words = (int32_t*)(n->ws + lay.row_words);
+        n->row_parts = row_parts(*desc);
+    }
     HIPCHK(hipGetDevice(&n->device));
     HIPCHK(hipDeviceGetAttribute(&n->num_cu, hipDeviceAttributeMultiprocessorCount, n->device));
     {
@@ -750,7 +788,7 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
         const int64_t nw = 2 * ((std::max<int64_t>(desc->max_rows, 1) + WIDE_TMIN - 1) / WIDE_TMIN);
         hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nw)), dim3(256), 0, s, n->wide_words, nw, 0);
     }
-    if (n->row) {
+    if (n->row_words) {
         const int64_t nw = std::max<int64_t>(desc->max_rows, 1);
         hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nw)), dim3(256), 0, s, n->row_words, nw, 0);
     }
@@ -885,6 +923,48 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
             n->row_perm = (uint8_t*)(n->ws + lay.row_perm);
             HIPCHK(hipMemcpyAsync(n->row_perm, perm.data(), perm.size(), hipMemcpyHostToDevice, s));
             HIPCHK(hipStreamSynchronize(s));
+        }
+    }
+    if (lay.rowc) {
+        // neuron pairs of the chunked one-row-tile kernel, paired on the host from
+        // per-neuron slot counts per chunk (computed on the device, max_rows layers at
+        // a time through the activation buffer)
+        const int C = rowc_chunks(*desc);
+        std::vector<uint32_t> hcnt((size_t)L * N);
+        const int64_t per = std::max<int64_t>(1, std::min<int64_t>(L, std::max<int64_t>(desc->max_rows, 1)));
+        for (int64_t l0 = 0; l0 < L; l0 += per) {
+            const int64_t nl = std::min<int64_t>(per, L - l0);
+            hipLaunchKernelGGL(k_rowc_counts, dim3(blocks_for(nl * N)), dim3(256), 0, s, idx + (size_t)l0 * N * K,
+                               nl * N, (int32_t)N, (int32_t)C, (uint32_t*)n->act);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(hcnt.data() + (size_t)l0 * N, n->act, (size_t)nl * N * 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        std::vector<uint32_t> pairs((size_t)L * N / 2);
+        const int worst = build_rowc_pairs(hcnt.data(), N, L, C, pairs.data());
+        if (worst >= 0 && worst <= ROWC_OVF_CAP) {
+            // the lane images, built on the device from the pairs (uploaded through the
+            // activation buffer, 2 max_rows layers at a time)
+            n->rowc_img = (uint32_t*)(n->ws + lay.rowc_img);
+            n->rowc_meta = (uint32_t*)(n->ws + lay.rowc_meta);
+            n->rowc_ovf = (uint32_t*)(n->ws + lay.rowc_ovf);
+            const int G = N / ROW_PART;
+            const int64_t per2 = std::max<int64_t>(1, std::min<int64_t>({(int64_t)L, 2 * std::max<int64_t>(desc->max_rows, 1),
+                                                                       (int64_t)65535}));
+            for (int64_t l0 = 0; l0 < L; l0 += per2) {
+                const int64_t nl = std::min<int64_t>(per2, L - l0);
+                HIPCHK(hipMemcpyAsync(n->act, pairs.data() + (size_t)l0 * N / 2, (size_t)nl * N / 2 * 4,
+                                      hipMemcpyHostToDevice, s));
+                const size_t lp = (size_t)l0 * G;
+                hipLaunchKernelGGL(k_rowc_build, dim3(G, (unsigned)nl), dim3(ROW_NT), 0, s, idx + (size_t)l0 * N * K,
+                                   w + (size_t)l0 * N * K, (const uint32_t*)n->act, (int32_t)N, (int32_t)C,
+                                   n->rowc_img + lp * ROWC_IMG * ROW_NT, n->rowc_meta + lp * ROW_NT * 4,
+                                   n->rowc_ovf + lp * ROWC_OVF_CAP * 2);
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipStreamSynchronize(s));
+            }
+            n->rowc = true;
+            n->rowc_chunks = C;
         }
     }
     n->variant = default_variant(n.get());
@@ -1034,6 +1114,9 @@ sdnn_status sdnn_tune(sdnn_net net, const float* y_sample, int64_t rows, void* s
             c.row_words = net->row_words;
             c.row_parts = net->row_parts;
             c.row_perm = net->row_perm;
+            c.rowc_img = net->rowc_img;
+            c.rowc_meta = net->rowc_meta;
+            c.rowc_ovf = net->rowc_ovf;
             init = mk((const void*)&k_chain_init, dim3(1), dim3(256), 0, net->cnt, (int32_t)1, (int32_t)rt,
                       (int32_t)c.compaction, net->bar, (int32_t)NBAR);
             run = mk(v.chain_fn, dim3(cg), dim3(v.NT), fwd_lds_bytes(v, N), c);

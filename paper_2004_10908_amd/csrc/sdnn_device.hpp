@@ -1,11 +1,57 @@
-// Device helpers shared by the forward kernel files: the acquire load of a
-// device counter, the persistent kernels' grid barrier and the per-layer
-// arguments of the persistent chain.
+// Device helpers shared by the forward kernel files: LDS access by absolute
+// address and the asynchronous global->LDS copies of the one-row-tile kernels, the
+// acquire load of a device counter, the persistent kernels' grid barrier and the
+// per-layer arguments of the persistent chain.
 #pragma once
 
 #include "sdnn_internal.hpp"
 
 namespace sdnn {
+
+// Absolute LDS byte addresses: the row kernels declare no static LDS, so their
+// dynamic LDS starts at address 0, and every LDS object is reached through a
+// pointer built from its address (never as an offset into a zero-length array).
+template <typename T>
+using lds_ptr = T __attribute__((address_space(3)))*;
+template <typename T>
+__device__ __forceinline__ lds_ptr<T> lds_at(uint32_t addr) {
+    return (lds_ptr<T>)(uintptr_t)addr;
+}
+
+__device__ __forceinline__ float row_lds_read(uint32_t addr) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return *reinterpret_cast<const float __attribute__((address_space(3)))*>(addr);
+#else
+    (void)addr;
+    return 0.f;
+#endif
+}
+
+// One 16-byte asynchronous copy per lane: global (scalar base + lane offset) ->
+// LDS at M0 + 16 * lane.
+__device__ __forceinline__ void row_copy16(uint64_t src, uint32_t voff, uint32_t dst) {
+    uint32_t saved;
+    __asm__ volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %1, %3\n\ts_mov_b32 m0, %0"
+                     : "=&s"(saved)
+                     : "v"(voff), "s"(dst), "s"(src)
+                     : "memory");
+}
+
+// One dword from src (a per-lane address) into LDS at M0 + 4 * lane.
+__device__ __forceinline__ void row_copy4(const int32_t* src, uint32_t dst) {
+    uint32_t saved;
+    __asm__ volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\tglobal_load_lds_dword %1, off\n\ts_mov_b32 m0, %0"
+                     : "=&s"(saved)
+                     : "v"(src), "s"(dst)
+                     : "memory");
+}
+
+__device__ __forceinline__ uint64_t uniform_ptr(const void* p) {
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
 
 __device__ __forceinline__ int ld_acquire(const int32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);

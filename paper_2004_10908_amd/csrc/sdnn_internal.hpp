@@ -56,6 +56,13 @@ struct LayerArgs {
     int32_t* row_words;
     int32_t row_parts;           // G: parts of ROW_PART neurons sharing a row
     const uint8_t* row_perm;     // [N][K] slot order of this layer (bank-scheduled variant), or null
+    // chunked one-row-tile kernel only, this layer's lane images built at create time:
+    // [parts][ROWC_IMG][ROW_NT] register words (64 weights, 32 packed offsets),
+    // [parts][ROW_NT][4] pair words (neurons, split, overflow counts, first entry),
+    // [parts][ROWC_OVF_CAP][2] overflow entries
+    const uint32_t* rowc_img;
+    const uint32_t* rowc_meta;
+    const uint32_t* rowc_ovf;
 };
 
 // Scheduled weight-gradient pass over one layer (rows are compact 0..R-1).
@@ -139,6 +146,9 @@ struct ChainArgs {
     int32_t* row_words;
     int32_t row_parts;
     const uint8_t* row_perm;     // [L][N][K] slot orders (bank-scheduled variant), or null
+    const uint32_t* rowc_img;    // chunked one-row-tile kernel: the lane images of every layer (see LayerArgs)
+    const uint32_t* rowc_meta;
+    const uint32_t* rowc_ovf;
 };
 
 // Error codes written to the device error word.
@@ -148,7 +158,8 @@ enum DeviceError : int32_t { DEV_OK = 0, DEV_BARRIER_TIMEOUT = 1 };
 struct FwdVariant {
     int T;          // rows per tile
     int NT;         // threads per workgroup
-    int staged;     // 5 = one-row tiles, bank-scheduled slot order; 4 = one-row tiles
+    int staged;     // 6 = one-row tiles staged in T chunks (rows wider than one LDS buffer),
+                    // ascending order; 5 = one-row tiles, bank-scheduled slot order; 4 = one-row tiles
                     // (resident weights), ascending order; 3 = wide (packed row tiles),
                     // 2 = scheduled resident-weight kernel,
                     // 1 = rows staged in LDS, 0 = direct gather
@@ -172,6 +183,31 @@ constexpr uint32_t ROW_STAGE = 2 * ROW_BUF_BYTES;        // two output stages of
 constexpr uint32_t ROW_SCAL = ROW_STAGE + 2 * ROW_PART * 4;
 constexpr size_t ROW_LDS = ROW_SCAL + 256;
 constexpr int ROW_GRID = 256;                            // one workgroup per CU, 8 XCDs x 32
+// The chunked one-row-tile kernel (sdnn_rowc.hip): the same parts of ROW_PART
+// neurons and ROW_NT lanes, for rows of 16384 < N <= 65536 floats staged in C = 2
+// or 4 chunks of N / C ids through the two row buffers.  A part's neurons form
+// ROW_NT pairs, one per lane; a pair's slots sit in 64 register positions, 64 / C
+// per chunk (first neuron's slots of the chunk, then the second's, padding of
+// weight 0); slots past a chunk's positions ("overflow") are kept as
+// (weight, offset | owner << 16) entries in LDS after the scalars.  The register
+// images are built once per net (k_rowc_build) from the ids, the weights and the
+// pairs the host chose.
+constexpr int ROWC_NMAX = 65536;
+constexpr int ROWC_IMG = 96;                                             // register words per lane
+constexpr uint32_t ROWC_OVF = ROW_SCAL + 256;                            // overflow entries (8 bytes)
+constexpr int ROWC_OVF_CAP = (int)((LDS_BYTES - ROWC_OVF) / 8);          // entries per workgroup
+constexpr size_t ROWC_LDS = LDS_BYTES;
+template <int C>
+__global__ void k_layer_rowc(LayerArgs a);
+template <int C>
+__global__ void k_chain_rowc(ChainArgs c);
+__global__ void k_rowc_counts(const int32_t* idx, int64_t neurons, int32_t N, int32_t C, uint32_t* counts);
+__global__ void k_rowc_build(const int32_t* idx, const float* w, const uint32_t* pairs, int32_t N, int32_t C,
+                             uint32_t* img, uint32_t* meta, uint32_t* ovf);
+// neuron pairs of the chunked kernel from per-neuron chunk counts (byte c of
+// counts[l][j] = slots of neuron j of layer l in chunk c): pairs [L][N / 2]; returns
+// the largest number of overflow entries of any part of any layer
+int build_rowc_pairs(const uint32_t* counts, int N, int L, int C, uint32_t* pairs);
 __global__ void k_layer_row(LayerArgs a);
 __global__ void k_chain_row(ChainArgs c);
 __global__ void k_layer_row_sched(LayerArgs a);
@@ -184,6 +220,7 @@ int fwd_variant_count();
 const FwdVariant& fwd_variant(int i);
 inline size_t fwd_lds_bytes(const FwdVariant& v, int N) {
     if (v.staged == 4 || v.staged == 5) return ROW_LDS;
+    if (v.staged == 6) return ROWC_LDS;
     return v.staged == 2 ? sched_lds_bytes(N) : (v.staged == 1 ? (size_t)v.T * N * sizeof(float) : 0);
 }
 

@@ -29,8 +29,10 @@
 #include <algorithm>
 #include <array>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <thread>
+#include <utility>
 #include <vector>
 
 #include "sdnn_internal.hpp"
@@ -315,6 +317,149 @@ int64_t build_row_schedule(const int32_t* idx, int N, int L, uint8_t* perm) {
     int64_t sum = 0;
     for (int64_t v : cost) sum += v;
     return sum;
+}
+
+// ---------------------------------------------------------------- neuron pairs
+// Neuron pairs of the chunked one-row-tile kernel (sdnn_rowc.hip).  A lane holds
+// two neurons in 64 register positions, 64 / C per chunk of the row; a pair whose
+// slots in a chunk exceed the chunk's positions keeps the excess in a per-part LDS
+// list, so pairs should complement each other: a neuron with many slots in some
+// chunks goes with one that has few there.  Per part (2048 neurons):
+//  * C = 2: the count in chunk 0 decides (chunk 1 has the rest), so pairing the
+//    i-th smallest count with the i-th largest balances every pair;
+//  * C = 4: neurons in order of decreasing imbalance (sum over chunks of
+//    |count - 8|) each take the unpaired partner with the least overflow (then
+//    the least squared deviation from 16 per chunk), searched among the count
+//    vectors within distance 2 (per chunk) of the ideal complement 16 - count,
+//    nearest first, or among all unpaired neurons when none is that close.
+namespace {
+
+uint32_t cnt_of(uint32_t v, int c) { return (v >> (8 * c)) & 0xffu; }
+
+// overflow entries and squared imbalance of a pair
+std::pair<int, int> pair_cost(uint32_t a, uint32_t b, int C) {
+    const int PC = 64 / C;
+    int ov = 0, dv = 0;
+    for (int c = 0; c < C; ++c) {
+        const int t = (int)(cnt_of(a, c) + cnt_of(b, c));
+        ov += t > PC ? t - PC : 0;
+        dv += (t - PC) * (t - PC);
+    }
+    return {ov, dv};
+}
+
+struct PairBuckets {
+    static constexpr int E = 33;            // count values 0..32
+    std::vector<std::vector<int>> bucket = std::vector<std::vector<int>>(E * E * E);
+    std::vector<int> where;                 // position of a neuron in its bucket
+    std::vector<int> touched;
+    static int key(uint32_t v) { return (int)(cnt_of(v, 0) * E * E + cnt_of(v, 1) * E + cnt_of(v, 2)); }
+    void add(int j, uint32_t v) {
+        auto& b = bucket[key(v)];
+        if (b.empty()) touched.push_back(key(v));
+        where[j] = (int)b.size();
+        b.push_back(j);
+    }
+    void remove(int j, uint32_t v) {
+        auto& b = bucket[key(v)];
+        const int at = where[j], last = b.back();
+        b[at] = last;
+        where[last] = at;
+        b.pop_back();
+    }
+    void clear() {
+        for (int k : touched) bucket[k].clear();
+        touched.clear();
+    }
+};
+
+// pairs of one part: out[lane] = first | second << 16 (neurons within the part);
+// returns the part's overflow entries
+int pair_part(const uint32_t* cnt, int n, int C, uint32_t* out, PairBuckets& pb) {
+    std::vector<int> order(n);
+    for (int j = 0; j < n; ++j) order[j] = j;
+    int total = 0, lanes = 0;
+    if (C == 2) {
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cnt_of(cnt[x], 0) < cnt_of(cnt[y], 0); });
+        for (int i = 0; i < n / 2; ++i) {
+            const int a = order[i], b = order[n - 1 - i];
+            out[lanes++] = (uint32_t)a | ((uint32_t)b << 16);
+            total += pair_cost(cnt[a], cnt[b], C).first;
+        }
+        return total;
+    }
+    const int PC = 64 / C;
+    auto imbalance = [&](int j) {
+        int e = 0;
+        for (int c = 0; c < C; ++c) e += std::abs((int)cnt_of(cnt[j], c) - PC / 2);
+        return e;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return imbalance(x) > imbalance(y); });
+    pb.where.assign(n, 0);
+    std::vector<char> used(n, 0);
+    for (int j = 0; j < n; ++j) pb.add(j, cnt[j]);
+    for (int i : order) {
+        if (used[i]) continue;
+        used[i] = 1;
+        pb.remove(i, cnt[i]);
+        const int u0 = PC - (int)cnt_of(cnt[i], 0), u1 = PC - (int)cnt_of(cnt[i], 1), u2 = PC - (int)cnt_of(cnt[i], 2);
+        int best = -1;
+        std::pair<int, int> bc{1 << 30, 1 << 30};
+        for (int r = 0; r <= 2; ++r) {
+            for (int d0 = -r; d0 <= r; ++d0)
+                for (int d1 = -r; d1 <= r; ++d1)
+                    for (int d2 = -r; d2 <= r; ++d2) {
+                        if (std::max(std::abs(d0), std::max(std::abs(d1), std::abs(d2))) != r) continue;
+                        const int v0 = u0 + d0, v1 = u1 + d1, v2 = u2 + d2;
+                        if (v0 < 0 || v1 < 0 || v2 < 0 || v0 > 32 || v1 > 32 || v2 > 32) continue;
+                        const auto& b = pb.bucket[v0 * PairBuckets::E * PairBuckets::E + v1 * PairBuckets::E + v2];
+                        if (b.empty()) continue;
+                        const int j = b.back();
+                        const auto c = pair_cost(cnt[i], cnt[j], C);
+                        if (c < bc) { bc = c; best = j; }
+                    }
+            if (best >= 0 && bc.first == 0) break;
+        }
+        if (best < 0) {
+            for (int j = 0; j < n; ++j)
+                if (!used[j]) {
+                    const auto c = pair_cost(cnt[i], cnt[j], C);
+                    if (c < bc) { bc = c; best = j; }
+                }
+        }
+        if (best < 0) break;                      // (n is even: never)
+        used[best] = 1;
+        pb.remove(best, cnt[best]);
+        out[lanes++] = (uint32_t)i | ((uint32_t)best << 16);
+        total += bc.first;
+    }
+    pb.clear();
+    return total;
+}
+
+}  // namespace
+
+int build_rowc_pairs(const uint32_t* counts, int N, int L, int C, uint32_t* pairs) {
+    if (N % ROW_PART != 0 || (C != 2 && C != 4) || L < 1) return -1;
+    const int G = N / ROW_PART;
+    const int64_t total = (int64_t)L * G;
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    nth = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nth, total));
+    std::vector<int> worst(nth, 0);
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nth; ++t) {
+        th.emplace_back([=, &worst] {
+            PairBuckets pb;
+            for (int64_t i = total * t / nth; i < total * (t + 1) / nth; ++i) {
+                const int l = (int)(i / G), p = (int)(i % G);
+                const uint32_t* cnt = counts + (size_t)l * N + (size_t)p * ROW_PART;
+                uint32_t* out = pairs + (size_t)l * (N / 2) + (size_t)p * (ROW_PART / 2);
+                worst[t] = std::max(worst[t], pair_part(cnt, ROW_PART, C, out, pb));
+            }
+        });
+    }
+    for (auto& x : th) x.join();
+    return *std::max_element(worst.begin(), worst.end());
 }
 
 }  // namespace sdnn

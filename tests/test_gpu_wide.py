@@ -36,10 +36,10 @@ def test_wide_forward_matches_oracle(P, N, layers, rows):
     y0 = torch.from_numpy(y0h).to(DEV)
     net = P.Net(idx, w, b, max_rows=rows, ckpt_every=1)
     if N > 16384:
-        assert net.plan["variant"] == 3, net.plan    # a row exceeds one 64 KB LDS buffer: the wide kernel
+        assert net.plan["variant"] == 6, net.plan    # a row exceeds one 64 KB LDS buffer: chunked one-row tiles
     else:
         assert net.plan["variant"] == 5, net.plan    # one-row tiles with resident weights
-        net.set_plan(32, 1024, 3)
+    net.set_plan(32, 1024, 3)
     base = None
     for m in MODES:
         o, nz, ys = forward_layers(net, y0, mode=m)
@@ -52,10 +52,11 @@ def test_wide_forward_matches_oracle(P, N, layers, rows):
 
 
 # Several tiles per workgroup (one-row-tile kernel at 16384 neurons, and the wide
-# kernel on the same net) and per XCD tile stream (wide kernel at 65536 neurons),
-# every layer of the chain checked element by element through its own activations.
+# kernel on the same net) and per XCD tile stream (chunked one-row-tile kernel and
+# wide kernel at 65536 neurons), every layer of the chain checked element by element
+# through its own activations.
 @pytest.mark.parametrize("N,layers,rows,plan", [(16384, 8, 2400, None), (16384, 6, 2400, (32, 1024, 3)),
-                                                (65536, 6, 1200, None)])
+                                                (65536, 6, 1200, None), (65536, 4, 1200, (32, 1024, 3))])
 def test_wide_chain_layer_sync_multi_tile(P, N, layers, rows, plan):
     cfg = gen.CONFIGS["S3"].with_(n_neurons=N, n_layers=layers, rows=rows, seed=N + rows + layers)
     idx, w, b = upload(cfg)
