@@ -67,7 +67,8 @@ typedef enum {
 
 /* sdnn_set_exec modes */
 #define SDNN_EXEC_AUTO         0 /* GRAPH for one batch, GRAPH_MERGED for several; PERSISTENT
-                                    on the wide-layer kernels (plan variant 3) */
+                                    on the wide-layer and chunked one-row-tile kernels (plan
+                                    variants 3 and 6) */
 #define SDNN_EXEC_EAGER        1 /* one kernel launch per layer, batches one after another */
 #define SDNN_EXEC_GRAPH        2 /* one hipGraph; batches one after another ("plain" form) */
 #define SDNN_EXEC_PERSISTENT   3 /* all layers of all batches in one cooperative kernel ("batched") */
@@ -95,8 +96,8 @@ typedef struct {
                                     that spreads a half-wave's LDS reads over distinct banks,
                                 6 = one-row tiles staged in rows_per_tile = 2 or 4 chunks,
                                     resident weights of create-time neuron pairs (forward-only
-                                    nets of 16384 < N <= 65536 neurons, N % 2048 == 0),
-                                    ascending slot order,
+                                    nets of 16384 < N <= 65536 neurons, N % 2048 == 0), each
+                                    chunk's slots in a create-time bank-spreading order,
                                 1 = direct gather (rows too wide for LDS),
                                 3 = wide layers: rows packed T per tile [N][T] in the workspace,
                                     one T*4-byte gather per slot (forward-only nets whose

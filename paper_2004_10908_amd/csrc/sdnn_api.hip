@@ -963,6 +963,12 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
                 HIPCHK(hipGetLastError());
                 HIPCHK(hipStreamSynchronize(s));
             }
+            // the bank order of every (layer, part, half-wave block)
+            const int64_t tasks = (int64_t)L * G * 32;
+            hipLaunchKernelGGL(k_rowc_sched, dim3((unsigned)std::min<int64_t>(4096, (tasks + 63) / 64)), dim3(64), 0, s,
+                               n->rowc_img, n->rowc_meta, tasks, (int32_t)C);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipStreamSynchronize(s));
             n->rowc = true;
             n->rowc_chunks = C;
         }
@@ -1071,7 +1077,7 @@ sdnn_status sdnn_tune(sdnn_net net, const float* y_sample, int64_t rows, void* s
     const bool chain = net->exec == SDNN_EXEC_PERSISTENT || net->exec == SDNN_EXEC_AUTO;
     // Variants of one family share the per-output arithmetic order (the scheduled
     // kernels sum slots in their create-time order), so tuning never changes results.
-    auto family = [](int staged) { return staged == 2 || staged == 5 ? staged : 0; };
+    auto family = [](int staged) { return staged == 2 || staged == 5 || staged == 6 ? staged : 0; };
     const int fam = family(var(net).staged);
     for (int vi = 0; vi < fwd_variant_count(); ++vi) {
         const FwdVariant& v = fwd_variant(vi);
@@ -1209,10 +1215,13 @@ sdnn_status sdnn_forward(sdnn_net net, const float* y0, int64_t rows, const int6
     int mode = net->exec;
     // the wide-layer kernels take two graph nodes per layer (pack, compute), empty
     // layers included; their persistent chain skips the empty ones (C4: 28.8 against
-    // 40.6 ms for the merged graph)
+    // 40.6 ms for the merged graph); the chunked one-row-tile kernel's layers load
+    // their lane images first, so its persistent chain also wins on the deep nets
+    // (C4: 20.6 against 26 ms)
     if (mode == SDNN_EXEC_AUTO)
-        mode = var(net).staged == 3 ? SDNN_EXEC_PERSISTENT
-                                    : (n_batches > 1 ? SDNN_EXEC_GRAPH_MERGED : SDNN_EXEC_GRAPH);
+        mode = (var(net).staged == 3 || var(net).staged == 6)
+                   ? SDNN_EXEC_PERSISTENT
+                   : (n_batches > 1 ? SDNN_EXEC_GRAPH_MERGED : SDNN_EXEC_GRAPH);
     if (mode == SDNN_EXEC_PERSISTENT) {
         Plan p = plan_persistent(net, y0, rows, y_out, nz_rows, n_nz, ckpt, layer_rows);
         return issue(p, s, net);

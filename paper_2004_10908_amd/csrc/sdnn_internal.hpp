@@ -188,10 +188,11 @@ constexpr int ROW_GRID = 256;                            // one workgroup per CU
 // or 4 chunks of N / C ids through the two row buffers.  A part's neurons form
 // ROW_NT pairs, one per lane; a pair's slots sit in 64 register positions, 64 / C
 // per chunk (first neuron's slots of the chunk, then the second's, padding of
-// weight 0); slots past a chunk's positions ("overflow") are kept as
+// weight 0, each part in a create-time order that spreads a half-wave's LDS reads
+// over the banks); slots past a chunk's positions ("overflow") are kept as
 // (weight, offset | owner << 16) entries in LDS after the scalars.  The register
-// images are built once per net (k_rowc_build) from the ids, the weights and the
-// pairs the host chose.
+// images are built once per net (k_rowc_build, then k_rowc_sched) from the ids,
+// the weights and the pairs the host chose.
 constexpr int ROWC_NMAX = 65536;
 constexpr int ROWC_IMG = 96;                                             // register words per lane
 constexpr uint32_t ROWC_OVF = ROW_SCAL + 256;                            // overflow entries (8 bytes)
@@ -204,6 +205,7 @@ __global__ void k_chain_rowc(ChainArgs c);
 __global__ void k_rowc_counts(const int32_t* idx, int64_t neurons, int32_t N, int32_t C, uint32_t* counts);
 __global__ void k_rowc_build(const int32_t* idx, const float* w, const uint32_t* pairs, int32_t N, int32_t C,
                              uint32_t* img, uint32_t* meta, uint32_t* ovf);
+__global__ void k_rowc_sched(uint32_t* img, uint32_t* meta, int64_t tasks, int32_t C);
 // neuron pairs of the chunked kernel from per-neuron chunk counts (byte c of
 // counts[l][j] = slots of neuron j of layer l in chunk c): pairs [L][N / 2]; returns
 // the largest number of overflow entries of any part of any layer

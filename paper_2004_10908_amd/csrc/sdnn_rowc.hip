@@ -103,12 +103,6 @@ __device__ __forceinline__ uint32_t rowc_addr(const RowcLane& n, int P, uint32_t
     return __builtin_amdgcn_perm(buf, n.o[P >> 1], (P & 1) ? 0x07060302u : 0x07060100u);
 }
 
-// The switch from A's sum to B's is a per-lane bit select (bit k of `onehot` set at
-// B's first position): a bitfield extract and two bit inserts.
-__device__ __forceinline__ float bit_select(uint32_t m, float x, float y) {
-    return __uint_as_float((m & __float_as_uint(x)) | (~m & __float_as_uint(y)));
-}
-
 template <int C, int CH, int RS, int G>
 __device__ __forceinline__ void rowc_reads(const RowcLane& n, uint32_t buf, float (&r)[RS]) {
     constexpr int PC = 64 / C;
@@ -116,42 +110,44 @@ __device__ __forceinline__ void rowc_reads(const RowcLane& n, uint32_t buf, floa
     for (int u = 0; u < RS; ++u) r[u] = row_lds_read(rowc_addr(n, PC * CH + RS * G + u, buf));
 }
 
+// The switch from A's sum to B's at the lane's switch position: a compare and two
+// selects per position (the position is opaque per chunk step, so the compares are
+// made there, not hoisted out of the row loop as 64 live lane masks).
 template <int C, int CH, int RS, int G>
-__device__ __forceinline__ void rowc_fmas(const RowcLane& n, uint32_t onehot, const float (&r)[RS], float& cur,
+__device__ __forceinline__ void rowc_fmas(const RowcLane& n, uint32_t splitc, const float (&r)[RS], float& cur,
                                           float& acca, float& accb) {
     constexpr int PC = 64 / C;
 #pragma unroll
     for (int u = 0; u < RS; ++u) {
         const int k = RS * G + u;
-        const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)onehot, (unsigned)k, 1u);
-        acca = bit_select(m, cur, acca);
-        cur = bit_select(m, accb, cur);
+        const bool sw = (uint32_t)k == splitc;
+        acca = sw ? cur : acca;
+        cur = sw ? accb : cur;
         cur = fmaf(n.w[PC * CH + k], r[u], cur);
     }
     __asm__ volatile("" : "+v"(cur), "+v"(acca), "+v"(accb) : : "memory");
 }
 
 template <int C, int CH, int RS, int G, typename Hook>
-__device__ __forceinline__ void rowc_group(const RowcLane& n, uint32_t buf, uint32_t onehot, float& cur, float& acca,
+__device__ __forceinline__ void rowc_group(const RowcLane& n, uint32_t buf, uint32_t splitc, float& cur, float& acca,
                                            float& accb, float (&v)[2][RS], Hook& hook) {
     constexpr int PC = 64 / C;
     hook(G);
     if constexpr (G + 1 < PC / RS) rowc_reads<C, CH, RS, G + 1>(n, buf, v[(G + 1) & 1]);
-    rowc_fmas<C, CH, RS, G>(n, onehot, v[G & 1], cur, acca, accb);
-    if constexpr (G + 1 < PC / RS) rowc_group<C, CH, RS, G + 1>(n, buf, onehot, cur, acca, accb, v, hook);
+    rowc_fmas<C, CH, RS, G>(n, splitc, v[G & 1], cur, acca, accb);
+    if constexpr (G + 1 < PC / RS) rowc_group<C, CH, RS, G + 1>(n, buf, splitc, cur, acca, accb, v, hook);
 }
 
 // Chunk CH of the row in the buffer at `buf`: its positions, then its overflow entries.
 template <int C, int CH, int RS, typename Hook>
 __device__ __forceinline__ void rowc_chunk(const RowcLane& n, uint32_t buf, float& acca, float& accb, Hook&& hook) {
     constexpr int PC = 64 / C;
-    const uint32_t splitc = byte_of(n.split, CH);
-    uint32_t onehot = 1u << splitc;               // bit PC (no switch) when A takes every position
-    __asm__ volatile("" : "+v"(onehot));
+    uint32_t splitc = byte_of(n.split, CH);          // PC: no switch in this chunk
+    __asm__ volatile("" : "+v"(splitc));
     float cur = acca;
     float v[2][RS];
     rowc_reads<C, CH, RS, 0>(n, buf, v[0]);
-    rowc_group<C, CH, RS, 0>(n, buf, onehot, cur, acca, accb, v, hook);
+    rowc_group<C, CH, RS, 0>(n, buf, splitc, cur, acca, accb, v, hook);
     // no switch to B in this chunk (A took every position): the running sum is A's
     const bool none = splitc == (uint32_t)PC;
     acca = none ? cur : acca;
@@ -213,11 +209,19 @@ __device__ __forceinline__ void run_layer_rowc(const LayerArgs& a, int R) {
     auto ring_row = [&](int i) -> int {
         return a.list_in ? __builtin_amdgcn_readfirstlane(s_ring[i % 3]) : pos_row(i);
     };
-    // this wave's k-th copy of a chunk (global address chunk_src) into the buffer at byte `buf`
+    // this wave's k-th copy of a chunk (global address chunk_src) into the buffer at
+    // byte `buf`.  The G parts of a row run on one XCD and stage the same chunk at
+    // about the same time; each starts at its own share of the chunk's 1 KB pieces
+    // (part p at piece p * ncopy / G), so they do not all ask the same L2 lines at
+    // once (C4 forward 23.5 -> 20.8 ms)
     const uint64_t ybase = uniform_ptr(a.yin);
+    const int rot = (int)(((int64_t)p * ncopy) / G);
     auto copy = [&](uint64_t chunk_src, uint32_t buf, int k) {
-        const int cc = wave + k * RC_WAVES;
-        if (cc < ncopy) row_copy16(chunk_src + 1024ull * (uint32_t)cc, 16u * (uint32_t)lane, buf + 1024u * (uint32_t)cc);
+        int cc = wave + k * RC_WAVES;
+        if (cc >= ncopy) return;
+        cc += rot;
+        if (cc >= ncopy) cc -= ncopy;
+        row_copy16(chunk_src + 1024ull * (uint32_t)cc, 16u * (uint32_t)lane, buf + 1024u * (uint32_t)cc);
     };
     auto chunk_src = [&](int row, int c) -> uint64_t {
         uint64_t s = ybase + 4ull * ((uint64_t)(uint32_t)row * (uint64_t)N + (uint64_t)(c * CW));
@@ -481,6 +485,136 @@ __global__ __launch_bounds__(ROW_NT) void k_rowc_build(const int32_t* idx, const
     for (int r = 0; r < 64; ++r) im[(size_t)r * ROW_NT] = __float_as_uint(wpos[r]);
     for (int r = 0; r < 32; ++r) im[(size_t)(64 + r) * ROW_NT] = opos[2 * r] | (opos[2 * r + 1] << 16);
     reinterpret_cast<uint4*>(meta)[pl * ROW_NT + tid] = make_uint4(pr, split, fits ? ocnt : 0u, (uint32_t)base);
+}
+
+// Bank order of the lane images: for one (layer, part, half-wave block of 32
+// lanes, chunk) per thread, the positions of the chunk are reordered so that at
+// each position the block's 32 lanes read few LDS banks twice (a 4-byte LDS read
+// is served per half-wave, bank = word address mod 32; in ascending order the 32
+// reads of a position hit random banks, about 3.5 passes per read).  A lane's
+// items are its A slots, its B slots and its padding (weight 0, which adds nothing
+// wherever it sits, so a zero-weight slot counts as padding too); B's slots may
+// only follow all of A's, so the lane's switch position becomes its first step
+// with a B slot.  Greedy per step: lanes with the fewest candidate banks choose
+// first, each the least-loaded bank among its candidates (padding may take any
+// bank, at a word of that bank).  Each neuron then sums its chunk's slots in this
+// fixed order, so results stay deterministic (they differ from ascending order
+// only by rounding).
+__global__ void k_rowc_sched(uint32_t* img, uint32_t* meta, int64_t tasks, int32_t C) {
+    const int PC = 64 / C;
+    // one thread per (layer, part, block) = task, its chunks in turn: the chunks of a
+    // block share the lanes' split words
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tasks; t += (int64_t)gridDim.x * blockDim.x) {
+        const int blk = (int)(t % 32);
+        const int64_t lp = t / 32;
+        uint32_t* im = img + lp * ROWC_IMG * ROW_NT + blk * 32;
+        uint32_t* me = meta + ((size_t)lp * ROW_NT + blk * 32) * 4;
+        for (int c = 0; c < C; ++c) {
+        // per lane: items (A's real slots, then B's) as (bank, source position); the
+        // choice per step: a source position, or 0x80 | bank for padding
+        uint8_t bank[32][32], srcp[32][32], outp[32][32];
+        int na[32], nb[32], npad[32], ra[32], rb[32], split[32];
+        uint32_t taken[32];
+        for (int l = 0; l < 32; ++l) {
+            const int m = (int)byte_of(me[4 * l + 1], c);
+            na[l] = nb[l] = 0;
+            for (int pass = 0; pass < 2; ++pass)
+                for (int k = pass ? m : 0; k < (pass ? PC : m); ++k) {
+                    const int pos = c * PC + k;
+                    const uint32_t w = im[(size_t)pos * ROW_NT + l];
+                    if ((w & 0x7fffffffu) == 0u) continue;             // padding or a zero weight
+                    const uint32_t ow = im[(size_t)(64 + pos / 2) * ROW_NT + l];
+                    const uint32_t off = (pos & 1) ? (ow >> 16) : (ow & 0xffffu);
+                    const int it = na[l] + nb[l];
+                    bank[l][it] = (uint8_t)((off >> 2) & 31u);
+                    srcp[l][it] = (uint8_t)k;
+                    if (pass) ++nb[l]; else ++na[l];
+                }
+            npad[l] = PC - na[l] - nb[l];
+            ra[l] = na[l];
+            rb[l] = nb[l];
+            split[l] = PC;
+            taken[l] = 0u;
+        }
+        for (int st = 0; st < PC; ++st) {
+            int load[32];
+            for (int q = 0; q < 32; ++q) load[q] = 0;
+            uint32_t cand[32];
+            int order[32], ncand[32];
+            for (int l = 0; l < 32; ++l) {
+                uint32_t mk = 0u;
+                const int b0 = ra[l] > 0 ? 0 : na[l], n = ra[l] > 0 ? na[l] : nb[l];
+                for (int i = 0; i < n; ++i)
+                    if (!((taken[l] >> (b0 + i)) & 1u)) mk |= 1u << bank[l][b0 + i];
+                cand[l] = mk;
+                ncand[l] = npad[l] > 0 ? 33 : __popc(mk);
+                order[l] = l;
+            }
+            for (int i = 1; i < 32; ++i)   // fewest candidates first (insertion sort, stable)
+                for (int j = i; j > 0 && ncand[order[j]] < ncand[order[j - 1]]; --j) {
+                    const int x = order[j];
+                    order[j] = order[j - 1];
+                    order[j - 1] = x;
+                }
+            for (int oi = 0; oi < 32; ++oi) {
+                const int l = order[oi];
+                int best = -1, bl = 1 << 30;
+                for (int q = 0; q < 32; ++q)
+                    if (((cand[l] >> q) & 1u) && load[q] < bl) { bl = load[q]; best = q; }
+                int pb = -1, pl = 1 << 30;
+                if (npad[l] > 0)
+                    for (int q = 0; q < 32; ++q)
+                        if (load[q] < pl) { pl = load[q]; pb = q; }
+                if (best < 0 || (pb >= 0 && pl < bl)) {        // padding on a freer bank
+                    outp[l][st] = (uint8_t)(0x80u | (uint32_t)pb);
+                    --npad[l];
+                    ++load[pb];
+                    continue;
+                }
+                const bool inA = ra[l] > 0;
+                const int b0 = inA ? 0 : na[l], n = inA ? na[l] : nb[l];
+                for (int i = 0; i < n; ++i) {
+                    const int it = b0 + i;
+                    if (((taken[l] >> it) & 1u) || bank[l][it] != (uint8_t)best) continue;
+                    taken[l] |= 1u << it;
+                    outp[l][st] = srcp[l][it];
+                    break;
+                }
+                if (inA) {
+                    --ra[l];
+                } else {
+                    if (split[l] == PC) split[l] = st;
+                    --rb[l];
+                }
+                ++load[best];
+            }
+        }
+        for (int l = 0; l < 32; ++l) {
+            uint32_t ow[32], oo[32];
+            for (int k = 0; k < PC; ++k) {
+                const int pos = c * PC + k;
+                ow[k] = im[(size_t)pos * ROW_NT + l];
+                const uint32_t o2 = im[(size_t)(64 + pos / 2) * ROW_NT + l];
+                oo[k] = (pos & 1) ? (o2 >> 16) : (o2 & 0xffffu);
+            }
+            for (int k = 0; k < PC; k += 2) {
+                uint32_t wk[2], ok[2];
+                for (int h = 0; h < 2; ++h) {
+                    const uint32_t src = outp[l][k + h];
+                    wk[h] = (src & 0x80u) ? 0u : ow[src];
+                    ok[h] = (src & 0x80u) ? 4u * (src & 31u) : oo[src];
+                }
+                const int pos = c * PC + k;
+                im[(size_t)pos * ROW_NT + l] = wk[0];
+                im[(size_t)(pos + 1) * ROW_NT + l] = wk[1];
+                im[(size_t)(64 + pos / 2) * ROW_NT + l] = (ok[0] & 0xffffu) | (ok[1] << 16);
+            }
+            uint32_t sp = me[4 * l + 1];
+            sp = (sp & ~(0xffu << (8 * c))) | ((uint32_t)split[l] << (8 * c));
+            me[4 * l + 1] = sp;
+        }
+        }
+    }
 }
 
 }  // namespace sdnn

@@ -1,10 +1,10 @@
 """Chunked one-row-tile kernel (16384 < N <= 65536, N a multiple of 2048; plan
-variant 6, rows staged in 2 or 4 chunks, paired neurons): every layer of its chain
-checked element by element against the oracle through the chain's own activations,
-with several rows per row stream; bitwise equal to the wide-layer kernel, which
-sums each neuron's slots in the same ascending order; the engines equal to each
+variant 6, rows staged in 2 or 4 chunks, paired neurons, a create-time bank order
+per chunk): every layer of its chain checked element by element against the oracle
+through the chain's own activations, with several rows per row stream, and the
+same for the wide-layer kernel on the same net; the engines bitwise equal to each
 other; a clamp the sums reach, a positive bias (no compaction), empty and one-row
-calls; the autotuner choosing within the family without changing any output."""
+calls; the autotuner leaving every output unchanged."""
 import numpy as np
 import pytest
 import torch
@@ -54,12 +54,10 @@ def test_rowc_chain_layer_sync(P, N, layers, rows, cfgname):
         else:
             assert torch.equal(o["y"], base[0]), m
             assert all(np.array_equal(a, c) for a, c in zip(ys, base[1])), m
-    # the wide-layer kernel sums each neuron's slots in the same ascending order: bitwise equal
+    # the wide-layer kernel on the same net (ascending order): also within the bounds
     net.set_plan(*WIDE)
-    for m in ("persistent", "graph"):
-        o, nz, ys = forward_layers(net, y0, batch_off=off, mode=m)
-        assert torch.equal(o["y"], base[0]), m
-        assert all(np.array_equal(a, c) for a, c in zip(ys, base[1])), m
+    o, nz, ys = forward_layers(net, y0, batch_off=off, mode="persistent")
+    check_chain(lay, cfg.clamp, ys, o["layer_rows"].cpu().numpy(), nz, y0h)
     net.close()
 
 
@@ -108,9 +106,9 @@ def test_rowc_empty_and_single_row(P):
 
 
 def test_rowc_family_autotune_on_the_workload(P):
-    """At 65536 neurons the chunked kernel, the wide-layer kernels and the direct
-    gather sum in the same order: timing them on the workload's rows picks a plan
-    and leaves every output bitwise unchanged."""
+    """At 65536 neurons the chunked kernel is alone in its family (its create-time
+    order): tuning on the workload's rows keeps it and leaves every output bitwise
+    unchanged."""
     N, rows = 65536, 256
     cfg = gen.CONFIGS["S4"].with_(n_neurons=N, n_layers=2, rows=rows, seed=37)
     idx, w, b = upload(cfg)
@@ -120,7 +118,7 @@ def test_rowc_family_autotune_on_the_workload(P):
     torch.cuda.synchronize()
     plan = net.tune(rows, y_sample=y0)
     print("tuned plan", plan, flush=True)
-    assert plan["tuned_us"] > 0
+    assert plan["tuned_us"] > 0 and plan["variant"] == 6
     c = net.forward(y0, batch_off=[0, 100, rows])
     torch.cuda.synchronize()
     assert torch.equal(a["y"], c["y"])
