@@ -144,6 +144,23 @@ int bwd_threads() { return BNT; }
 const void* bwd_dw_fn() { return (const void*)&k_bwd_dw; }
 const void* bwd_dy_fn() { return (const void*)&k_bwd_dy; }
 
+// sum_{g < P} p[g * stride] in g order, with up to 16 loads in flight (a loop that
+// adds each value as it arrives waits out one memory latency per partial)
+__device__ inline float sum_partials(const float* p, int P, size_t stride) {
+    constexpr int U = 16;
+    float s = 0.f;
+    int g = 0;
+    for (; g + U <= P; g += U) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = p[(size_t)(g + u) * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += v[u];
+    }
+    for (; g < P; ++g) s += p[(size_t)g * stride];
+    return s;
+}
+
 // dW[j][k] = sum_{g < P} pdw[g][j][k] (in g order); db likewise.
 __global__ void k_reduce_partials(const float* pdw, const float* pdb, int32_t P, int32_t N, float* dw, float* db,
                                   const int32_t* nrows, int32_t T) {
@@ -153,16 +170,10 @@ __global__ void k_reduce_partials(const float* pdw, const float* pdb, int32_t P,
     if (nrows) P = min(P, (*nrows + T - 1) / T);
     const int64_t nk = (int64_t)N * K;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nk + N; e += (int64_t)gridDim.x * blockDim.x) {
-        if (e < nk) {
-            float s = 0.f;
-            for (int g = 0; g < P; ++g) s += pdw[(size_t)g * nk + e];
-            dw[e] = s;
-        } else {
-            const int64_t j = e - nk;
-            float s = 0.f;
-            for (int g = 0; g < P; ++g) s += pdb[(size_t)g * N + j];
-            db[j] = s;
-        }
+        if (e < nk)
+            dw[e] = sum_partials(pdw + e, P, (size_t)nk);
+        else
+            db[e - nk] = sum_partials(pdb + (e - nk), P, (size_t)N);
     }
 }
 

@@ -270,15 +270,20 @@ __global__ __launch_bounds__(256) void k_fin_zero(const int32_t* alive, int32_t 
 // (L-1-l) is even and the workspace buffer otherwise, so the last layer always
 // lands in y_out.
 template <int T, int NT, bool STAGED>
-__global__ __launch_bounds__(NT) void k_chain(ChainArgs c) {
+__global__ __launch_bounds__(NT) void k_chain(ChainArgs) {
     extern __shared__ __align__(16) float lds[];
     __shared__ int s_ok;
     unsigned gen = 0u;
-    for (int l = 0; l < c.L; ++l) {
-        const int R = (l == 0 || !c.compaction) ? c.rows : ld_acquire(&c.cnt[l]);
-        if (R == 0) break;
-        const LayerArgs a = chain_layer_args(c, l, R);
-        run_layer<T, NT, STAGED>(a, lds, blockIdx.x, gridDim.x, R);
+    for (int l = 0;; ++l) {
+        {
+            const ChainArgs c = reload_chain_args();
+            if (l >= c.L) break;
+            const int R = (l == 0 || !c.compaction) ? c.rows : ld_count(&c.cnt[l]);
+            if (R == 0) break;
+            const LayerArgs a = chain_layer_args(c, l, R);
+            run_layer<T, NT, STAGED>(a, lds, blockIdx.x, gridDim.x, R);
+        }
+        const ChainArgs c = reload_chain_args();
         if (!grid_barrier(c.bar, gen, c.err, &s_ok)) return;
     }
     // the nz list and the row profile are produced by the finalize passes after this kernel
@@ -474,18 +479,28 @@ __global__ __launch_bounds__(NT) void k_layer_wide(LayerArgs a) {
 
 // Persistent chain of the wide kernels: pack, grid barrier, compute, grid barrier.
 template <int T, int NT>
-__global__ __launch_bounds__(NT) void k_chain_wide(ChainArgs c) {
+__global__ __launch_bounds__(NT) void k_chain_wide(ChainArgs) {
     __shared__ int s_ok;
     unsigned gen = 0u;
-    for (int l = 0; l < c.L; ++l) {
-        const int R = (l == 0 || !c.compaction) ? c.rows : ld_acquire(&c.cnt[l]);
-        if (R == 0) break;
-        const LayerArgs a = chain_layer_args(c, l, R);
-        wide_pack_body<T>(a, R, blockIdx.x, gridDim.x);
-        if (!grid_barrier(c.bar, gen, c.err, &s_ok)) return;
-        // run_layer_wide returns early only in workgroups with no share of any tile,
-        // which then wait at the barrier below like the others
-        run_layer_wide<T, NT, wide_unroll<NT, true>()>(a, blockIdx.x, gridDim.x, R);
+    for (int l = 0;; ++l) {
+        int R;
+        {
+            const ChainArgs c = reload_chain_args();
+            if (l >= c.L) break;
+            R = (l == 0 || !c.compaction) ? c.rows : ld_count(&c.cnt[l]);
+            if (R == 0) break;
+            const LayerArgs a = chain_layer_args(c, l, R);
+            wide_pack_body<T>(a, R, blockIdx.x, gridDim.x);
+            if (!grid_barrier(c.bar, gen, c.err, &s_ok)) return;
+        }
+        {
+            // run_layer_wide returns early only in workgroups with no share of any tile,
+            // which then wait at the barrier below like the others
+            const ChainArgs c = reload_chain_args();
+            const LayerArgs a = chain_layer_args(c, l, R);
+            run_layer_wide<T, NT, wide_unroll<NT, true>()>(a, blockIdx.x, gridDim.x, R);
+        }
+        const ChainArgs c = reload_chain_args();
         if (!grid_barrier(c.bar, gen, c.err, &s_ok)) return;
     }
 }
@@ -1103,45 +1118,28 @@ __global__ __launch_bounds__(NT) void k_layer_sched(LayerArgs a) {
 }
 
 template <int NT, int DMAX>
-__global__ __launch_bounds__(NT) void k_chain_sched(ChainArgs c) {
+__global__ __launch_bounds__(NT) void k_chain_sched(ChainArgs) {
     extern __shared__ __align__(16) float lds[];
     unsigned gen = 0u;
-    const int N = c.N, L = c.L;
-    const size_t NK = (size_t)N * K;
-    const size_t npad = (size_t)c.nblk * 64;
-    for (int l = 0; l < L; ++l) {
-        const int R = (l == 0 || !c.compaction) ? c.rows : ld_acquire(&c.cnt[l]);
-        if (R == 0) break;
-        const bool out_is_y = ((L - 1 - l) & 1) == 0;
-        LayerArgs a{};
-        a.yin = l == 0 ? c.y0 : (out_is_y ? c.act : c.y_out);
-        a.yout = out_is_y ? c.y_out : c.act;
-        a.ycopy = (c.ckpt && (l + 1) % c.ckpt_every == 0 && l + 1 < L)
-                      ? c.ckpt + (size_t)((l + 1) / c.ckpt_every - 1) * c.rows * N
-                      : nullptr;
-        a.dead_mark = (c.compaction && !out_is_y) ? -1 : 0;
-        a.idx = c.idx + l * NK;
-        a.w = c.w + l * NK;
-        a.b = c.b + (size_t)l * N;
-        a.list_in = (l == 0 || !c.compaction) ? nullptr : ((l & 1) ? c.list1 : c.list0);
-        a.list_out = c.compaction ? (((l + 1) & 1) ? c.list1 : c.list0) : nullptr;
-        a.cnt_in = nullptr;
-        a.cnt_out = &c.cnt[l + 1];
-        a.alive = c.alive;
-        a.row_base = 0;
-        a.nrows = R;
-        a.N = N;
-        a.layer = l;
-        a.clamp = c.clamp;
-        a.ent = c.ent + (size_t)l * npad * SCHED_DSTORE;
-        a.lane_neuron = c.lane_neuron + (size_t)l * npad;
-        a.wave_steps = c.wave_steps + (size_t)l * c.nblk;
-        a.tile_bits = c.tile_bits;
-        a.prog = c.prog;
-        a.parts = c.parts;
-        a.nblk = c.nblk;
-        run_layer_sched<NT, DMAX>(a, lds, R);
-        if (!grid_barrier(c.bar, gen, c.err, reinterpret_cast<int*>(lds + sched_tile_bytes(N) / 4) + 4)) return;
+    for (int l = 0;; ++l) {
+        {
+            const ChainArgs c = reload_chain_args();
+            if (l >= c.L) break;
+            const int R = (l == 0 || !c.compaction) ? c.rows : ld_count(&c.cnt[l]);
+            if (R == 0) break;
+            const size_t npad = (size_t)c.nblk * 64;
+            LayerArgs a = chain_layer_args(c, l, R);
+            a.ent = c.ent + (size_t)l * npad * SCHED_DSTORE;
+            a.lane_neuron = c.lane_neuron + (size_t)l * npad;
+            a.wave_steps = c.wave_steps + (size_t)l * c.nblk;
+            a.tile_bits = c.tile_bits;
+            a.prog = c.prog;
+            a.parts = c.parts;
+            a.nblk = c.nblk;
+            run_layer_sched<NT, DMAX>(a, lds, R);
+        }
+        const ChainArgs c = reload_chain_args();
+        if (!grid_barrier(c.bar, gen, c.err, reinterpret_cast<int*>(lds + sched_tile_bytes(c.N) / 4) + 4)) return;
     }
 }
 

@@ -201,11 +201,23 @@ __device__ __forceinline__ void run_layer_row(const LayerArgs& a, int R) {
     auto ring_row = [&](int i) -> int {
         return a.list_in ? __builtin_amdgcn_readfirstlane(s_ring[i % 3]) : pos_row(i);
     };
-    // copies of row `row` into the buffer at byte `buf`: this wave's k-th copy
-    auto copy = [&](int row, uint32_t buf, int k) {
-        const int c = wave + k * WAVES;
-        const uint64_t src = uniform_ptr(a.yin + (size_t)row * N + (size_t)c * 256);
-        if (c * 256 + 4 * lane < N) row_copy16(src, 16u * (uint32_t)lane, buf + 1024u * (uint32_t)c);
+    // copies of a row (global address src) into the buffer at byte `buf`: this wave's
+    // k-th copy.  The row address and the wave index are opaque to the compiler, so
+    // it recomputes each copy's address from them instead of holding one 64-bit
+    // address per copy across the tile loop (in the persistent chain those were
+    // spilled to VGPR lanes and read back one v_readlane at a time: 1.65 x the time
+    // per layer)
+    const uint64_t ybase = uniform_ptr(a.yin);
+    auto row_src = [&](int row) -> uint64_t {
+        uint64_t s = ybase + 4ull * (uint64_t)(uint32_t)row * (uint64_t)(uint32_t)N;
+        __asm__ volatile("" : "+s"(s));
+        return s;
+    };
+    auto copy = [&](uint64_t src, uint32_t buf, int k) {
+        int w = wave;
+        __asm__ volatile("" : "+s"(w));
+        const int c = w + k * WAVES;
+        if (c * 256 + 4 * lane < N) row_copy16(src + 1024ull * (uint32_t)c, 16u * (uint32_t)lane, buf + 1024u * (uint32_t)c);
     };
 
     // wave 0's liveness pipeline: A = tile whose word add is in flight, B = tile
@@ -261,7 +273,10 @@ __device__ __forceinline__ void run_layer_row(const LayerArgs& a, int R) {
     __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
     __syncthreads();
     int row_c = ring_row(0);
-    for (int k = 0; k < mycopies; ++k) copy(row_c, 0u, k);
+    {
+        const uint64_t src = row_src(row_c);
+        for (int k = 0; k < mycopies; ++k) copy(src, 0u, k);
+    }
     int row_p = 0;
     for (int i = 0; i < ntile; ++i) {
         uint32_t buf = (uint32_t)(i & 1) * ROW_BUF_BYTES;
@@ -280,13 +295,14 @@ __device__ __forceinline__ void run_layer_row(const LayerArgs& a, int R) {
         const bool more = i + 1 < ntile;
         const int row_n = more ? ring_row(i + 1) : 0;
         if (i + 2 < ntile) prefetch(i + 2);
+        const uint64_t nsrc = row_src(row_n);
         float acc0 = 0.f, acc1 = 0.f;
         auto hook = [&](int g) {
-            if (more && g < mycopies) copy(row_n, buf ^ ROW_BUF_BYTES, g);
+            if (more && g < mycopies) copy(nsrc, buf ^ ROW_BUF_BYTES, g);
         };
         row_steps<RS>(n0, n1, buf, acc0, acc1, hook);
         if (more)
-            for (int k = K / RS; k < mycopies; ++k) copy(row_n, buf ^ ROW_BUF_BYTES, k);
+            for (int k = K / RS; k < mycopies; ++k) copy(nsrc, buf ^ ROW_BUF_BYTES, k);
         const float y0 = fminf(fmaxf(acc0 + n0.bj, 0.f), a.clamp);
         const float y1 = fminf(fmaxf(acc1 + n1.bj, 0.f), a.clamp);
         const lds_ptr<float> st = stage + (i & 1) * ROW_PART;
@@ -314,17 +330,23 @@ __device__ __forceinline__ void run_layer_row(const LayerArgs& a, int R) {
 }
 
 template <bool PERM>
-__device__ __forceinline__ void chain_row(const ChainArgs& c) {
+__device__ __forceinline__ void chain_row() {
     int* s_ok = (int*)lds_at<int>(ROW_S_OK);
     unsigned gen = 0u;
-    for (int l = 0; l < c.L; ++l) {
-        const int R = (l == 0 || !c.compaction) ? c.rows : ld_acquire(&c.cnt[l]);
-        if (R == 0) break;
-        LayerArgs a = chain_layer_args(c, l, R);
-        a.row_parts = c.row_parts;
-        a.row_words = c.row_words;
-        a.row_perm = c.row_perm ? c.row_perm + (size_t)l * c.N * K : nullptr;
-        run_layer_row<PERM, 2>(a, R);
+    for (int l = 0;; ++l) {
+        int R;
+        {
+            const ChainArgs c = reload_chain_args();
+            if (l >= c.L) break;
+            R = (l == 0 || !c.compaction) ? c.rows : ld_count(&c.cnt[l]);
+            if (R == 0) break;
+            LayerArgs a = chain_layer_args(c, l, R);
+            a.row_parts = c.row_parts;
+            a.row_words = c.row_words;
+            a.row_perm = c.row_perm ? c.row_perm + (size_t)l * c.N * K : nullptr;
+            run_layer_row<PERM, 4>(a, R);
+        }
+        const ChainArgs c = reload_chain_args();
         if (!grid_barrier(c.bar, gen, c.err, s_ok)) return;
     }
 }
@@ -332,10 +354,10 @@ __device__ __forceinline__ void chain_row(const ChainArgs& c) {
 __global__ __launch_bounds__(ROW_NT) void k_layer_row(LayerArgs a) {
     run_layer_row<false, 4>(a, a.cnt_in ? *a.cnt_in : a.nrows);
 }
-__global__ __launch_bounds__(ROW_NT) void k_chain_row(ChainArgs c) { chain_row<false>(c); }
+__global__ __launch_bounds__(ROW_NT) void k_chain_row(ChainArgs) { chain_row<false>(); }
 __global__ __launch_bounds__(ROW_NT) void k_layer_row_sched(LayerArgs a) {
     run_layer_row<true, 4>(a, a.cnt_in ? *a.cnt_in : a.nrows);
 }
-__global__ __launch_bounds__(ROW_NT) void k_chain_row_sched(ChainArgs c) { chain_row<true>(c); }
+__global__ __launch_bounds__(ROW_NT) void k_chain_row_sched(ChainArgs) { chain_row<true>(); }
 
 }  // namespace sdnn

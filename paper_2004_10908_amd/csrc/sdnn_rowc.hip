@@ -362,23 +362,31 @@ __device__ __forceinline__ void rowc_layer_tables(const ChainArgs& c, int l, Lay
     a.rowc_ovf = c.rowc_ovf + (size_t)l * parts * ROWC_OVF_CAP * 2;
 }
 
+#ifndef RC_CHAIN_RS
+#define RC_CHAIN_RS 2
+#endif
 template <int C>
 __global__ __launch_bounds__(ROW_NT) void k_layer_rowc(LayerArgs a) {
     run_layer_rowc<C, 4>(a, a.cnt_in ? *a.cnt_in : a.nrows);
 }
 
 template <int C>
-__global__ __launch_bounds__(ROW_NT) void k_chain_rowc(ChainArgs c) {
+__global__ __launch_bounds__(ROW_NT) void k_chain_rowc(ChainArgs) {
     int* s_ok = (int*)lds_at<int>(RC_S_OK);
     unsigned gen = 0u;
-    for (int l = 0; l < c.L; ++l) {
-        const int R = (l == 0 || !c.compaction) ? c.rows : ld_acquire(&c.cnt[l]);
-        if (R == 0) break;
-        LayerArgs a = chain_layer_args(c, l, R);
-        a.row_parts = c.row_parts;
-        a.row_words = c.row_words;
-        rowc_layer_tables(c, l, a);
-        run_layer_rowc<C, 2>(a, R);
+    for (int l = 0;; ++l) {
+        {
+            const ChainArgs c = reload_chain_args();
+            if (l >= c.L) break;
+            const int R = (l == 0 || !c.compaction) ? c.rows : ld_count(&c.cnt[l]);
+            if (R == 0) break;
+            LayerArgs a = chain_layer_args(c, l, R);
+            a.row_parts = c.row_parts;
+            a.row_words = c.row_words;
+            rowc_layer_tables(c, l, a);
+            run_layer_rowc<C, RC_CHAIN_RS>(a, R);
+        }
+        const ChainArgs c = reload_chain_args();
         if (!grid_barrier(c.bar, gen, c.err, s_ok)) return;
     }
 }
