@@ -147,9 +147,9 @@ __device__ __forceinline__ void row_group(const RowNeuron& n0, const RowNeuron& 
     if constexpr (G + 1 < K / RS) row_group<RS, G + 1>(n0, n1, buf, acc0, acc1, v, hook);
 }
 
-// RS: slots per group.  Four (eight reads in flight per wave) is faster for the
-// per-layer launch (S3 merged graph 546 against 580 ms); the persistent chain,
-// whose layer loop keeps more registers live, spills at four and takes two.
+// RS: slots per group.  Four (eight reads in flight per wave) is faster than two
+// (S3 merged graph 546 against 580 ms), in the per-layer launch and, since the chain
+// reads its arguments again per layer, in the persistent chain.
 template <int RS, typename Hook>
 __device__ __forceinline__ void row_steps(const RowNeuron& n0, const RowNeuron& n1, uint32_t buf, float& acc0,
                                           float& acc1, Hook&& hook) {
