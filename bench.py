@@ -520,6 +520,14 @@ def bench_streams(args, torch, P, gen, dev):
         y = torch.empty_like(y0)
         for cap in (False, True):
             for k in ((1, 2, 4) if not cap else (1, 2, 4, 8)):
+                # each stream's net holds its own workspace (at 65536 neurons, lane
+                # images of 26 GB): skip a stream count whose nets would not fit
+                free = torch.cuda.mem_get_info(dev)[0]
+                if k * net.ws_bytes > 0.85 * free:
+                    r[("captured" if cap else "eager") + f"_{k}"] = {
+                        "skipped": f"{k} stream nets need up to {k * net.ws_bytes / 2**30:.0f} GiB, "
+                                   f"{free / 2**30:.0f} GiB free"}
+                    continue
                 sf = StreamForward(idx, w, b, off, k, capture=cap)
                 sf.run(y0, y)
                 torch.cuda.synchronize()
@@ -534,6 +542,8 @@ def bench_streams(args, torch, P, gen, dev):
                                                                   "workspace_MB": round(sf.workspace_bytes / 2**20, 1),
                                                                   "equal_to_graph": same}
                 sf.close()
+                del sf
+                torch.cuda.empty_cache()                  # (the next stream count's nets need the room)
         sres[name] = r
         log("streams " + name, r)
         net.close()
