@@ -146,6 +146,8 @@ def chain_kernel_name(plan):
         return "sdnn::k_chain_row_sched"
     if v == 6:
         return f"sdnn::k_chain_rowc<{T}>"
+    if v == 7:
+        return f"sdnn::k_chain_rowu<{T}>"
     return f"sdnn::k_chain<{T}, {NT}, {'true' if v == 0 else 'false'}>"
 
 

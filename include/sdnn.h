@@ -68,7 +68,7 @@ typedef enum {
 /* sdnn_set_exec modes */
 #define SDNN_EXEC_AUTO         0 /* GRAPH for one batch, GRAPH_MERGED for several; PERSISTENT
                                     on the wide-layer and chunked one-row-tile kernels (plan
-                                    variants 3 and 6) */
+                                    variants 3, 6 and 7) */
 #define SDNN_EXEC_EAGER        1 /* one kernel launch per layer, batches one after another */
 #define SDNN_EXEC_GRAPH        2 /* one hipGraph; batches one after another ("plain" form) */
 #define SDNN_EXEC_PERSISTENT   3 /* all layers of all batches in one cooperative kernel ("batched") */
@@ -98,6 +98,10 @@ typedef struct {
                                     resident weights of create-time neuron pairs (forward-only
                                     nets of 16384 < N <= 65536 neurons, N % 2048 == 0), each
                                     chunk's slots in a create-time bank-spreading order,
+                                7 = the same images, two parts of 2048 neurons per workgroup
+                                    (nets of variant 6 whose every layer has a single weight
+                                    value, N % 4096 == 0; the default there; outputs equal
+                                    variant 6's),
                                 1 = direct gather (rows too wide for LDS),
                                 3 = wide layers: rows packed T per tile [N][T] in the workspace,
                                     one T*4-byte gather per slot (forward-only nets whose

@@ -273,6 +273,7 @@ struct sdnn_net_s {
     bool rowc = false;                  // chunked one-row-tile kernel available (images built)
     uint32_t *rowc_img = nullptr, *rowc_meta = nullptr, *rowc_ovf = nullptr;   // its lane images [L][...]
     int rowc_chunks = 0;
+    bool rowu = false;                  // every layer has one weight value: the two-part kernel serves it
     uint32_t* ent = nullptr;
     int32_t *lane_neuron = nullptr, *wave_steps = nullptr, *tile_bits = nullptr, *prog = nullptr;
     int parts = 1, nblk = 0;
@@ -312,6 +313,7 @@ sdnn_status host_error(const sdnn_net_s* n) {
 }
 
 bool variant_fits(const sdnn_net_s* n, const FwdVariant& v) {
+    if (v.staged == 7) return n->rowc && n->rowu && v.T == n->rowc_chunks;
     if (v.staged == 6) return n->rowc && v.T == n->rowc_chunks;
     if (v.staged == 5) return n->row && n->row_perm;
     if (v.staged == 4) return n->row;
@@ -370,7 +372,7 @@ sdnn_status prepare_variant(sdnn_net_s* n, int vi, int* grid, int* chain_grid) {
         *grid = SCHED_GRID;
         *chain_grid = SCHED_GRID;
     }
-    if (v.staged == 4 || v.staged == 5 || v.staged == 6) {
+    if (v.staged >= 4 && v.staged <= 7) {
         // one workgroup per CU, mapped to (XCD, part, stream) like the scheduled kernels
         if (*grid < ROW_GRID || *chain_grid < ROW_GRID)
             return fail(SDNN_EUNSUPPORTED, "one-row-tile kernel needs %d co-resident workgroups", ROW_GRID);
@@ -393,9 +395,13 @@ int default_variant(const sdnn_net_s* n) {
             for (int i = 0; i < fwd_variant_count(); ++i)
                 if (fwd_variant(i).staged == want) return i;
         }
+    // the two-part kernel stages each row half as often (C4 layer: 6.6 against 10.3 ms)
     if (n->rowc)
-        for (int i = 0; i < fwd_variant_count(); ++i)
-            if (fwd_variant(i).staged == 6 && fwd_variant(i).T == n->rowc_chunks) return i;
+        for (int want : {7, 6}) {
+            if (want == 7 && !n->rowu) continue;
+            for (int i = 0; i < fwd_variant_count(); ++i)
+                if (fwd_variant(i).staged == want && fwd_variant(i).T == n->rowc_chunks) return i;
+        }
     int best = -1, bestT = 0;
     for (int i = 0; i < fwd_variant_count(); ++i) {
         const FwdVariant& v = fwd_variant(i);
@@ -951,6 +957,8 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
             const int G = N / ROW_PART;
             const int64_t per2 = std::max<int64_t>(1, std::min<int64_t>({(int64_t)L, 2 * std::max<int64_t>(desc->max_rows, 1),
                                                                        (int64_t)65535}));
+            int32_t* status = n->flag + 3;                 // set by the builder if a list overflowed
+            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, status, (int64_t)1, 0);
             for (int64_t l0 = 0; l0 < L; l0 += per2) {
                 const int64_t nl = std::min<int64_t>(per2, L - l0);
                 HIPCHK(hipMemcpyAsync(n->act, pairs.data() + (size_t)l0 * N / 2, (size_t)nl * N / 2 * 4,
@@ -959,7 +967,7 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
                 hipLaunchKernelGGL(k_rowc_build, dim3(G, (unsigned)nl), dim3(ROW_NT), 0, s, idx + (size_t)l0 * N * K,
                                    w + (size_t)l0 * N * K, (const uint32_t*)n->act, (int32_t)N, (int32_t)C,
                                    n->rowc_img + lp * ROWC_IMG * ROW_NT, n->rowc_meta + lp * ROW_NT * 4,
-                                   n->rowc_ovf + lp * ROWC_OVF_CAP * 2);
+                                   n->rowc_ovf + lp * ROWC_OVF_CAP * 2, status);
                 HIPCHK(hipGetLastError());
                 HIPCHK(hipStreamSynchronize(s));
             }
@@ -968,9 +976,31 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
             hipLaunchKernelGGL(k_rowc_sched, dim3((unsigned)std::min<int64_t>(4096, (tasks + 63) / 64)), dim3(64), 0, s,
                                n->rowc_img, n->rowc_meta, tasks, (int32_t)C);
             HIPCHK(hipGetLastError());
+            int32_t over = 0;
+            HIPCHK(hipMemcpyAsync(&over, status, 4, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            n->rowc = true;
+            n->rowc = over == 0;
             n->rowc_chunks = C;
+        }
+        // the two-part kernel: whole pairs of parts and one weight value per layer (the
+        // per-layer flags go through the activation buffer)
+        if (n->rowc && (N / ROW_PART) % 2 == 0 && (size_t)L <= (size_t)std::max<int64_t>(desc->max_rows, 1) * N) {
+            int32_t* flags = (int32_t*)n->act;
+            hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(L)), dim3(256), 0, s, flags, (int64_t)L, 0);
+            hipLaunchKernelGGL(k_weights_uniform, dim3(blocks_for(nnz)), dim3(256), 0, s, w, (int64_t)N * K, nnz, flags);
+            HIPCHK(hipGetLastError());
+            std::vector<int32_t> hf((size_t)L);
+            HIPCHK(hipMemcpyAsync(hf.data(), flags, (size_t)L * 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (std::all_of(hf.begin(), hf.end(), [](int32_t f) { return f == 0; })) {
+                // padding reads the chunk buffer's last word, which that kernel keeps zero
+                const int64_t lanes = (int64_t)L * (N / ROW_PART) * ROW_NT;
+                hipLaunchKernelGGL(k_rowu_pads, dim3(blocks_for(lanes)), dim3(256), 0, s, n->rowc_img, lanes,
+                                   (uint32_t)(4 * (N / C - 1)));
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipStreamSynchronize(s));
+                n->rowu = true;
+            }
         }
     }
     n->variant = default_variant(n.get());
@@ -1077,7 +1107,7 @@ sdnn_status sdnn_tune(sdnn_net net, const float* y_sample, int64_t rows, void* s
     const bool chain = net->exec == SDNN_EXEC_PERSISTENT || net->exec == SDNN_EXEC_AUTO;
     // Variants of one family share the per-output arithmetic order (the scheduled
     // kernels sum slots in their create-time order), so tuning never changes results.
-    auto family = [](int staged) { return staged == 2 || staged == 5 || staged == 6 ? staged : 0; };
+    auto family = [](int staged) { return staged == 2 || staged == 5 || staged == 6 || staged == 7 ? staged : 0; };
     const int fam = family(var(net).staged);
     for (int vi = 0; vi < fwd_variant_count(); ++vi) {
         const FwdVariant& v = fwd_variant(vi);
@@ -1219,7 +1249,7 @@ sdnn_status sdnn_forward(sdnn_net net, const float* y0, int64_t rows, const int6
     // their lane images first, so its persistent chain also wins on the deep nets
     // (C4: 20.6 against 26 ms)
     if (mode == SDNN_EXEC_AUTO)
-        mode = (var(net).staged == 3 || var(net).staged == 6)
+        mode = (var(net).staged == 3 || var(net).staged == 6 || var(net).staged == 7)
                    ? SDNN_EXEC_PERSISTENT
                    : (n_batches > 1 ? SDNN_EXEC_GRAPH_MERGED : SDNN_EXEC_GRAPH);
     if (mode == SDNN_EXEC_PERSISTENT) {

@@ -1477,6 +1477,8 @@ static const FwdVariant g_variants[] = {
     {1, ROW_NT, 5, (const void*)&k_layer_row_sched, (const void*)&k_chain_row_sched, nullptr},
     {2, ROW_NT, 6, (const void*)&k_layer_rowc<2>, (const void*)&k_chain_rowc<2>, nullptr},
     {4, ROW_NT, 6, (const void*)&k_layer_rowc<4>, (const void*)&k_chain_rowc<4>, nullptr},
+    {2, ROW_NT, 7, (const void*)&k_layer_rowu<2>, (const void*)&k_chain_rowu<2>, nullptr},
+    {4, ROW_NT, 7, (const void*)&k_layer_rowu<4>, (const void*)&k_chain_rowu<4>, nullptr},
 };
 #undef SDNN_V
 #undef SDNN_VD

@@ -158,7 +158,8 @@ enum DeviceError : int32_t { DEV_OK = 0, DEV_BARRIER_TIMEOUT = 1 };
 struct FwdVariant {
     int T;          // rows per tile
     int NT;         // threads per workgroup
-    int staged;     // 6 = one-row tiles staged in T chunks (rows wider than one LDS buffer),
+    int staged;     // 7 = as 6, two parts per workgroup, one weight per layer;
+                    // 6 = one-row tiles staged in T chunks (rows wider than one LDS buffer),
                     // ascending order; 5 = one-row tiles, bank-scheduled slot order; 4 = one-row tiles
                     // (resident weights), ascending order; 3 = wide (packed row tiles),
                     // 2 = scheduled resident-weight kernel,
@@ -204,7 +205,16 @@ template <int C>
 __global__ void k_chain_rowc(ChainArgs c);
 __global__ void k_rowc_counts(const int32_t* idx, int64_t neurons, int32_t N, int32_t C, uint32_t* counts);
 __global__ void k_rowc_build(const int32_t* idx, const float* w, const uint32_t* pairs, int32_t N, int32_t C,
-                             uint32_t* img, uint32_t* meta, uint32_t* ovf);
+                             uint32_t* img, uint32_t* meta, uint32_t* ovf, int32_t* status);
+// The uniform-weight two-part kernel (sdnn_rowc.hip): the chunked kernel's lane
+// images, two parts per workgroup (4096 neurons), for nets whose layers each have a
+// single weight value; N % 4096 == 0.
+template <int C>
+__global__ void k_layer_rowu(LayerArgs a);
+template <int C>
+__global__ void k_chain_rowu(ChainArgs c);
+__global__ void k_rowu_pads(uint32_t* img, int64_t lanes, uint32_t zoff);
+__global__ void k_weights_uniform(const float* w, int64_t per_layer, int64_t total, int32_t* flags);
 __global__ void k_rowc_sched(uint32_t* img, uint32_t* meta, int64_t tasks, int32_t C);
 // neuron pairs of the chunked kernel from per-neuron chunk counts (byte c of
 // counts[l][j] = slots of neuron j of layer l in chunk c): pairs [L][N / 2]; returns
@@ -222,7 +232,7 @@ int fwd_variant_count();
 const FwdVariant& fwd_variant(int i);
 inline size_t fwd_lds_bytes(const FwdVariant& v, int N) {
     if (v.staged == 4 || v.staged == 5) return ROW_LDS;
-    if (v.staged == 6) return ROWC_LDS;
+    if (v.staged == 6 || v.staged == 7) return ROWC_LDS;
     return v.staged == 2 ? sched_lds_bytes(N) : (v.staged == 1 ? (size_t)v.T * N * sizeof(float) : 0);
 }
 

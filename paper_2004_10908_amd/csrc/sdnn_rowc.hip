@@ -393,6 +393,374 @@ template __global__ void k_layer_rowc<4>(LayerArgs);
 template __global__ void k_chain_rowc<2>(ChainArgs);
 template __global__ void k_chain_rowc<4>(ChainArgs);
 
+// ---------------------------------------------------------------- uniform-weight two-part kernel
+// For nets whose layers each carry one weight value w (the sparse-DNN challenge's
+// nets have one weight for every connection), the register positions need no
+// weights: a lane holds the offsets of two pairs, pair l of sub-parts 2p and 2p + 1
+// of the chunked kernel's lane images, so a workgroup computes 4096 neurons and each
+// row is staged from L2 once per 4096 neurons instead of once per 2048 (the staging
+// is what bounds the chunked kernel at 65536 neurons).  What differs from it:
+//  * padding positions read a zero word: the last 16 bytes of every staged chunk go
+//    to a side slot instead of the buffer, so the buffer's last word stays zero; the
+//    builder makes every slot on those 4 ids an overflow entry, and k_rowu_pads
+//    points the padding offsets at that word once per net;
+//  * overflow entries are 4 bytes (offset | owner << 16 | side << 17), the lists of
+//    both sub-parts in the LDS one part's 8-byte list takes;
+//  * one output stage of 4096 floats: it is written after the last chunk step of a
+//    row and read after the first barrier of the next one, C - 1 >= 1 barriers later.
+// Every neuron sums its slots in the images' order with fused multiply-adds by w, as
+// the chunked kernel does with the same images (padding adds w * 0 here and 0 * y
+// there), so the two give equal outputs.
+namespace {
+
+constexpr uint32_t RU_SIDE = ROW_SCAL + 128;                     // [2][16 bytes], one per buffer
+constexpr uint32_t RU_OVF_HALF = (uint32_t)ROWC_OVF_CAP * 4u;    // one sub-part's 4-byte entries
+
+struct RowuPair {
+    uint32_t o[32];    // 64 positions: 16-bit LDS byte offsets within the chunk buffer
+    uint32_t split;    // byte c: positions of neuron A in chunk c (B's follow)
+    uint32_t ocnt;     // byte c: overflow entries of chunk c
+    uint32_t obase;    // LDS byte address of the pair's first overflow entry
+    uint32_t jab;      // neurons A (low 16 bits) and B (high) within the sub-part
+    float ba, bb;
+};
+
+// Pair `tid` of sub-part sp (0 or 1) of the workgroup, image part `ip`; the
+// sub-part's overflow list goes to LDS with the side bit set on entries of a chunk's
+// last 4 ids.
+__device__ __forceinline__ void rowu_load(const LayerArgs& a, int ip, int sp, int tid, int CW, RowuPair& n) {
+    const uint32_t* img = a.rowc_img + (size_t)ip * ROWC_IMG * ROW_NT + tid;
+#pragma unroll
+    for (int r = 0; r < 32; ++r) n.o[r] = img[(size_t)(64 + r) * ROW_NT];
+    const uint4 m = reinterpret_cast<const uint4*>(a.rowc_meta)[(size_t)ip * ROW_NT + tid];
+    n.jab = m.x;
+    n.split = m.y;
+    n.ocnt = m.z;
+    n.obase = ROWC_OVF + (uint32_t)sp * RU_OVF_HALF + 4u * m.w;
+    n.ba = a.b[ip * ROW_PART + (int)(m.x & 0xffffu)];
+    n.bb = a.b[ip * ROW_PART + (int)(m.x >> 16)];
+    const uint2* src = reinterpret_cast<const uint2*>(a.rowc_ovf + (size_t)ip * ROWC_OVF_CAP * 2);
+    const uint32_t last = 4u * (uint32_t)(CW - 4);
+    for (int e = tid; e < ROWC_OVF_CAP; e += ROW_NT) {
+        const uint32_t y = src[e].y;
+        *lds_at<uint32_t>(ROWC_OVF + (uint32_t)sp * RU_OVF_HALF + 4u * (uint32_t)e) =
+            y | ((y & 0xffffu) >= last ? (1u << 17) : 0u);
+    }
+}
+
+__device__ __forceinline__ uint32_t rowu_addr(const RowuPair& n, int P, uint32_t buf) {
+    return __builtin_amdgcn_perm(buf, n.o[P >> 1], (P & 1) ? 0x07060302u : 0x07060100u);
+}
+
+template <int C, int CH, int RS, int G>
+__device__ __forceinline__ void rowu_reads(const RowuPair& n, uint32_t buf, float (&r)[RS]) {
+    constexpr int PC = 64 / C;
+#pragma unroll
+    for (int u = 0; u < RS; ++u) r[u] = row_lds_read(rowu_addr(n, PC * CH + RS * G + u, buf));
+}
+
+template <int RS, int G>
+__device__ __forceinline__ void rowu_fmas(float wu, uint32_t splitc, const float (&r)[RS], float& cur, float& acca,
+                                          float& accb) {
+#pragma unroll
+    for (int u = 0; u < RS; ++u) {
+        const int k = RS * G + u;
+        const bool sw = (uint32_t)k == splitc;
+        acca = sw ? cur : acca;
+        cur = sw ? accb : cur;
+        cur = fmaf(wu, r[u], cur);
+    }
+    __asm__ volatile("" : "+v"(cur), "+v"(acca), "+v"(accb) : : "memory");
+}
+
+template <int C, int CH, int RS, int G, typename Hook>
+__device__ __forceinline__ void rowu_group(const RowuPair& n, float wu, uint32_t buf, uint32_t splitc, float& cur,
+                                           float& acca, float& accb, float (&v)[2][RS], Hook& hook) {
+    constexpr int PC = 64 / C;
+    hook(G);
+    if constexpr (G + 1 < PC / RS) rowu_reads<C, CH, RS, G + 1>(n, buf, v[(G + 1) & 1]);
+    rowu_fmas<RS, G>(wu, splitc, v[G & 1], cur, acca, accb);
+    if constexpr (G + 1 < PC / RS) rowu_group<C, CH, RS, G + 1>(n, wu, buf, splitc, cur, acca, accb, v, hook);
+}
+
+// Chunk CH of the row (buffer at `buf`, its last 16 bytes at `side`) for one pair:
+// its positions, then its overflow entries.
+template <int C, int CH, int RS, typename Hook>
+__device__ __forceinline__ void rowu_chunk(const RowuPair& n, float wu, uint32_t buf, uint32_t side, float& acca,
+                                           float& accb, Hook&& hook) {
+    constexpr int PC = 64 / C;
+    uint32_t splitc = byte_of(n.split, CH);
+    __asm__ volatile("" : "+v"(splitc));
+    float cur = acca;
+    float v[2][RS];
+    rowu_reads<C, CH, RS, 0>(n, buf, v[0]);
+    rowu_group<C, CH, RS, 0>(n, wu, buf, splitc, cur, acca, accb, v, hook);
+    const bool none = splitc == (uint32_t)PC;
+    acca = none ? cur : acca;
+    accb = none ? accb : cur;
+    const int cnt = (int)byte_of(n.ocnt, CH);
+    uint32_t ea = n.obase;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) ea += 4u * byte_of(n.ocnt, c);
+    for (int e = 0; e < cnt; ++e) {
+        const uint32_t en = *lds_at<uint32_t>(ea + 4u * (uint32_t)e);
+        const uint32_t off = en & 0xffffu;
+        const float x = row_lds_read((en >> 17) ? side + (off & 15u) : (buf | off));
+        if ((en >> 16) & 1u)
+            accb = fmaf(wu, x, accb);
+        else
+            acca = fmaf(wu, x, acca);
+    }
+}
+
+}  // namespace
+
+template <int C, int RS>
+__device__ __forceinline__ void run_layer_rowu(const LayerArgs& a, int R) {
+    const int N = a.N;
+    const int CW = N / C;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int G = a.row_parts / 2;                     // parts of 2 ROW_PART neurons (the host keeps row_parts even)
+    if (G < 1) return;
+    const int b = blockIdx.x, x = b & 7, kk = b >> 3;
+    const int spx = (int)(gridDim.x >> 3) / G;        // row streams per XCD group
+    if (kk >= spx * G) return;                         // no part of any stream (uniform)
+    const int p = kk % G;
+    const int q = (kk / G) * 8 + x;
+    const int S = spx * 8;
+    if (q >= R) return;
+    const int ntile = (R - q + S - 1) / S;             // this stream's rows: positions q, q + S, ...
+    const int pbase = p * 2 * ROW_PART;
+
+    const lds_ptr<unsigned> s_bits = lds_at<unsigned>(RC_S_BITS);
+    const lds_ptr<int> s_ring = lds_at<int>(RC_S_RING);
+    const lds_ptr<float> stage = lds_at<float>(ROW_STAGE);   // [2 ROW_PART], one stage
+
+    // the layer's weight (every weight of the layer has this value)
+    const float wu = __uint_as_float((uint32_t)__builtin_amdgcn_readfirstlane((int)__float_as_uint(a.w[0])));
+    RowuPair n0, n1;
+    rowu_load(a, 2 * p, 0, tid, CW, n0);
+    rowu_load(a, 2 * p + 1, 1, tid, CW, n1);
+#pragma unroll
+    for (int s = 0; s < 32; ++s) __asm__ volatile("" : "+v"(n0.o[s]), "+v"(n1.o[s]));   // keep resident
+    // the zero words: the last 16 bytes of both buffers, which no copy writes
+    if (tid < 8) *lds_at<float>((uint32_t)(tid >> 2) * ROW_BUF_BYTES + 4u * (uint32_t)(CW - 4 + (tid & 3))) = 0.f;
+
+    const int ncopy = CW / 256;                        // 1 KB copies per chunk
+    const int mycopies = wave < ncopy ? (ncopy - wave + RC_WAVES - 1) / RC_WAVES : 0;
+    auto pos_row = [&](int i) -> int { return a.row_base + q + i * S; };   // identity work list
+    auto prefetch = [&](int i) {
+        if (a.list_in && wave == 0 && lane == 0) row_copy4(a.list_in + q + i * S, RC_S_RING + 4u * (uint32_t)(i % 3));
+    };
+    auto ring_row = [&](int i) -> int {
+        return a.list_in ? __builtin_amdgcn_readfirstlane(s_ring[i % 3]) : pos_row(i);
+    };
+    const uint64_t ybase = uniform_ptr(a.yin);
+    const int rot = (int)(((int64_t)p * ncopy) / G);
+    // this wave's k-th copy of a chunk into the buffer at byte `buf`; the chunk's last
+    // piece leaves its last 16 bytes (lane 63's) to the buffer's side slot
+    auto copy = [&](uint64_t chunk_src, uint32_t buf, uint32_t side, int k) {
+        int cc = wave + k * RC_WAVES;
+        if (cc >= ncopy) return;
+        cc += rot;
+        if (cc >= ncopy) cc -= ncopy;
+        const uint64_t src = chunk_src + 1024ull * (uint32_t)cc;
+        const uint32_t dst = buf + 1024u * (uint32_t)cc;
+        if (cc != ncopy - 1 || lane < 63)
+            row_copy16(src, 16u * (uint32_t)lane, dst);
+        else
+            row_copy16(src, 16u * (uint32_t)lane, side - 16u * 63u);   // lands at `side`
+    };
+    auto chunk_src = [&](int row, int c) -> uint64_t {
+        uint64_t s = ybase + 4ull * ((uint64_t)(uint32_t)row * (uint64_t)N + (uint64_t)(c * CW));
+        __asm__ volatile("" : "+s"(s));
+        return s;
+    };
+
+    // wave 0's liveness pipeline (as in the one-row-tile kernel)
+    int posA = -1, rowA = 0, posB = -1, rowB = 0;
+    unsigned bitA = 0u, retA = 0u;
+    int retB = 0;
+    auto advance = [&](int pos_new, int row_new, unsigned bit_new) {
+        const unsigned oldA = (unsigned)__builtin_amdgcn_readfirstlane((int)retA);
+        const int base = __builtin_amdgcn_readfirstlane(retB);
+        if (posB >= 0) {
+            if (lane == 0) a.list_out[base] = rowB;
+            posB = -1;
+        }
+        if (posA >= 0) {
+            if ((int)(oldA >> 16) == G - 1) {          // this part completed the row
+                const bool any = ((oldA & 0xffffu) + bitA) != 0u;
+                if (lane == 0) {
+                    if (G > 1) atomicExch(&a.row_words[posA], 0);
+                    if (a.alive) a.alive[rowA] = any ? 1 : a.dead_mark;
+                }
+                if (any && a.list_out) {
+                    retB = lane == 0 ? atomicAdd(a.cnt_out, 1) : 0;
+                    rowB = rowA;
+                    posB = posA;
+                }
+            }
+            posA = -1;
+        }
+        if (pos_new >= 0) {
+            retA = 0u;
+            if (G > 1 && lane == 0) retA = (unsigned)atomicAdd(&a.row_words[pos_new], (int)((1u << 16) | bit_new));
+            bitA = bit_new;
+            rowA = row_new;
+            posA = pos_new;
+        }
+    };
+    // the previous row's outputs: the part's 4096 floats as 16-byte stores
+    auto store_stage = [&](int row) {
+        const int e = 4 * tid;
+        const lds_ptr<const float> sp = lds_at<const float>(ROW_STAGE + 4u * (uint32_t)e);
+        const float4 v = make_float4(sp[0], sp[1], sp[2], sp[3]);
+        const size_t o = (size_t)row * N + pbase + e;
+        *reinterpret_cast<float4*>(a.yout + o) = v;
+        if (a.ycopy) *reinterpret_cast<float4*>(a.ycopy + o) = v;
+    };
+
+    if (tid == 0) { s_bits[0] = 0u; s_bits[1] = 0u; }
+    prefetch(0);
+    if (ntile > 1) prefetch(1);
+    __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
+    __syncthreads();                                   // overflow lists, zero words and row ids are in place
+    int row_c = ring_row(0);
+    {
+        const uint64_t cs = chunk_src(row_c, 0);
+        for (int k = 0; k < mycopies; ++k) copy(cs, 0u, RU_SIDE, k);
+    }
+    int row_p = 0;
+    for (int i = 0; i < ntile; ++i) {
+        const bool more = i + 1 < ntile;
+        int row_n = 0;
+        float acca0 = 0.f, accb0 = 0.f, acca1 = 0.f, accb1 = 0.f;
+        auto step = [&](auto cc) {
+            constexpr int CH = decltype(cc)::value;
+            uint32_t buf = (uint32_t)(CH & 1) * ROW_BUF_BYTES;
+            __asm__ volatile("" : "+s"(buf));
+            const uint32_t side = RU_SIDE + 16u * (uint32_t)(CH & 1);
+            __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");   // this wave's copies of the chunk have landed
+            __syncthreads();                                        // everyone's have; the other buffer is free
+            if constexpr (CH == 0) {
+                if (i > 0) {
+                    if (wave == 0) {
+                        const unsigned bit = s_bits[(i - 1) & 1];
+                        advance(q + (i - 1) * S, row_p, bit);       // before any store: nothing outstanding
+                        if (lane == 0) s_bits[(i - 1) & 1] = 0u;
+                    }
+                    store_stage(row_p);
+                }
+                row_n = more ? ring_row(i + 1) : 0;
+                if (i + 2 < ntile) prefetch(i + 2);
+            }
+            // the next chunk step's copies, all issued before the first compute group
+            const bool next = CH + 1 < C || more;
+            const uint64_t nsrc = chunk_src(CH + 1 < C ? row_c : row_n, CH + 1 < C ? CH + 1 : 0);
+            const uint32_t nbuf = (uint32_t)((CH + 1) & 1) * ROW_BUF_BYTES;
+            const uint32_t nside = RU_SIDE + 16u * (uint32_t)((CH + 1) & 1);
+            int myc = next ? mycopies : 0;
+            __asm__ volatile("" : "+s"(myc));
+            auto hook = [&](int g) {
+                if (g == 0)
+                    for (int k = 0; k < myc; ++k) copy(nsrc, nbuf, nside, k);
+            };
+            auto nohook = [](int) {};
+            rowu_chunk<C, CH, RS>(n0, wu, buf, side, acca0, accb0, hook);
+            rowu_chunk<C, CH, RS>(n1, wu, buf, side, acca1, accb1, nohook);
+        };
+        step(std::integral_constant<int, 0>{});
+        step(std::integral_constant<int, 1>{});
+        if constexpr (C == 4) {
+            step(std::integral_constant<int, 2>{});
+            step(std::integral_constant<int, 3>{});
+        }
+        const float ya0 = fminf(fmaxf(acca0 + n0.ba, 0.f), a.clamp);
+        const float yb0 = fminf(fmaxf(accb0 + n0.bb, 0.f), a.clamp);
+        const float ya1 = fminf(fmaxf(acca1 + n1.ba, 0.f), a.clamp);
+        const float yb1 = fminf(fmaxf(accb1 + n1.bb, 0.f), a.clamp);
+        stage[n0.jab & 0xffffu] = ya0;
+        stage[n0.jab >> 16] = yb0;
+        stage[ROW_PART + (n1.jab & 0xffffu)] = ya1;
+        stage[ROW_PART + (n1.jab >> 16)] = yb1;
+        const bool nz = ya0 != 0.f || yb0 != 0.f || ya1 != 0.f || yb1 != 0.f;
+        if (__ballot(nz) != 0ull && lane == 0)
+            __hip_atomic_fetch_or(s_bits + (i & 1), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        row_p = row_c;
+        row_c = row_n;
+    }
+    // drain: the last row's outputs and the rest of the liveness pipeline
+    __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
+    __syncthreads();
+    if (wave == 0) {
+        advance(q + (ntile - 1) * S, row_p, s_bits[(ntile - 1) & 1]);
+        __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
+        advance(-1, 0, 0u);
+        __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
+        advance(-1, 0, 0u);
+    }
+    store_stage(row_p);
+    __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");
+    __syncthreads();                                   // the LDS is reused by the next layer
+}
+
+template <int C>
+__global__ __launch_bounds__(ROW_NT) void k_layer_rowu(LayerArgs a) {
+    run_layer_rowu<C, 2>(a, a.cnt_in ? *a.cnt_in : a.nrows);
+}
+
+template <int C>
+__global__ __launch_bounds__(ROW_NT) void k_chain_rowu(ChainArgs) {
+    int* s_ok = (int*)lds_at<int>(RC_S_OK);
+    unsigned gen = 0u;
+    for (int l = 0;; ++l) {
+        {
+            const ChainArgs c = reload_chain_args();
+            if (l >= c.L) break;
+            const int R = (l == 0 || !c.compaction) ? c.rows : ld_count(&c.cnt[l]);
+            if (R == 0) break;
+            LayerArgs a = chain_layer_args(c, l, R);
+            a.row_parts = c.row_parts;
+            a.row_words = c.row_words;
+            rowc_layer_tables(c, l, a);
+            run_layer_rowu<C, 2>(a, R);
+        }
+        const ChainArgs c = reload_chain_args();
+        if (!grid_barrier(c.bar, gen, c.err, s_ok)) return;
+    }
+}
+
+template __global__ void k_layer_rowu<2>(LayerArgs);
+template __global__ void k_layer_rowu<4>(LayerArgs);
+template __global__ void k_chain_rowu<2>(ChainArgs);
+template __global__ void k_chain_rowu<4>(ChainArgs);
+
+// Points every padding position (weight 0) of the lane images at byte offset `zoff`
+// of the chunk buffer, the zero word of the uniform-weight kernel (the chunked
+// kernel multiplies padding by 0 wherever it points).  One thread per lane image.
+__global__ void k_rowu_pads(uint32_t* img, int64_t lanes, uint32_t zoff) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < lanes; t += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t* im = img + (t / ROW_NT) * (int64_t)ROWC_IMG * ROW_NT + t % ROW_NT;
+        for (int r = 0; r < 32; ++r) {
+            uint32_t o = im[(size_t)(64 + r) * ROW_NT];
+            if ((im[(size_t)(2 * r) * ROW_NT] & 0x7fffffffu) == 0u) o = (o & 0xffff0000u) | zoff;
+            if ((im[(size_t)(2 * r + 1) * ROW_NT] & 0x7fffffffu) == 0u) o = (o & 0xffffu) | (zoff << 16);
+            im[(size_t)(64 + r) * ROW_NT] = o;
+        }
+    }
+}
+
+// flags[l] = 1 where some weight of layer l differs (bitwise) from the layer's first.
+__global__ void k_weights_uniform(const float* w, int64_t per_layer, int64_t total, int32_t* flags) {
+    const uint32_t* wb = reinterpret_cast<const uint32_t*>(w);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t l = i / per_layer;
+        if (wb[i] != wb[l * per_layer]) flags[l] = 1;
+    }
+}
+
 // Per-neuron slot counts per chunk (byte c) of `neurons` consecutive neurons of N
 // inputs each (several layers stacked): the host pairs neurons from them.
 __global__ void k_rowc_counts(const int32_t* idx, int64_t neurons, int32_t N, int32_t C, uint32_t* counts) {
@@ -411,12 +779,14 @@ __global__ void k_rowc_counts(const int32_t* idx, int64_t neurons, int32_t N, in
 // The lane images of one (part, layer) = (blockIdx.x, blockIdx.y), one thread per
 // pair (lane): positions per chunk (A's slots, then B's, then weight-0 padding),
 // the pair words and the part's overflow list, entries of a lane in chunk order
-// (A's excess, then B's) and lanes in order.  A list longer than ROWC_OVF_CAP (the
-// host checks the counts first, so never) keeps only what fits, and a lane whose
-// entries do not all fit keeps none.
+// (A's excess, then B's) and lanes in order.  Slots on a chunk's last 4 ids are
+// always overflow entries (the uniform-weight kernel keeps those 16 bytes of a
+// staged chunk outside the buffer and a zero word in their place).  A list longer
+// than ROWC_OVF_CAP keeps only what fits, a lane whose entries do not all fit keeps
+// none, and `status` is set to 1 (the host then does not use the images).
 __global__ __launch_bounds__(ROW_NT) void k_rowc_build(const int32_t* idx, const float* w, const uint32_t* pairs,
                                                        int32_t N, int32_t C, uint32_t* img, uint32_t* meta,
-                                                       uint32_t* ovf) {
+                                                       uint32_t* ovf, int32_t* status) {
     __shared__ int s_tot[RC_WAVES];
     const int p = blockIdx.x, l = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int parts = gridDim.x;
@@ -425,19 +795,22 @@ __global__ __launch_bounds__(ROW_NT) void k_rowc_build(const int32_t* idx, const
     const int j[2] = {p * ROW_PART + (int)(pr & 0xffffu), p * ROW_PART + (int)(pr >> 16)};
     const int32_t* ids[2] = {idx + ((size_t)l * N + j[0]) * K, idx + ((size_t)l * N + j[1]) * K};
     const float* ws[2] = {w + ((size_t)l * N + j[0]) * K, w + ((size_t)l * N + j[1]) * K};
-    int cnt[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    // slots per chunk, and those that may take a position (not on the chunk's last 4 ids)
+    int cnt[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, cntp[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
     for (int h = 0; h < 2; ++h)
         for (int k = 0; k < K; ++k) {
-            const int c = min(max(ids[h][k], 0) / CW, C - 1);
+            const int id = max(ids[h][k], 0);
+            const int c = min(id / CW, C - 1);
             cnt[h][c] += 1;
+            cntp[h][c] += (id - c * CW < CW - 4) ? 1 : 0;
         }
     uint32_t split = 0u, ocnt = 0u;
     int tot = 0;
     int m[4] = {0, 0, 0, 0};
     for (int c = 0; c < C; ++c) {
-        m[c] = min(cnt[0][c], PC);
+        m[c] = min(cntp[0][c], PC);
         const int ova = cnt[0][c] - m[c];
-        const int ovb = max(0, cnt[1][c] - (PC - m[c]));
+        const int ovb = cnt[1][c] - min(cntp[1][c], PC - m[c]);
         split |= (uint32_t)m[c] << (8 * c);
         ocnt |= (uint32_t)(ova + ovb) << (8 * c);
         tot += ova + ovb;
@@ -453,6 +826,7 @@ __global__ __launch_bounds__(ROW_NT) void k_rowc_build(const int32_t* idx, const
     int base = v - tot;
     for (int x = 0; x < wave; ++x) base += s_tot[x];
     const bool fits = base + tot <= ROWC_OVF_CAP;
+    if (!fits) atomicOr(status, 1);
     const size_t pl = (size_t)l * parts + p;
     uint32_t* im = img + pl * ROWC_IMG * ROW_NT + tid;
     uint32_t* ov = ovf + pl * ROWC_OVF_CAP * 2;
@@ -474,9 +848,10 @@ __global__ __launch_bounds__(ROW_NT) void k_rowc_build(const int32_t* idx, const
                 const int id = ids[h][k];
                 if (min(max(id, 0) / CW, C - 1) != c) continue;
                 const uint32_t off = (4u * (uint32_t)(id - c * CW)) & 0xffffu;
-                if (rank < room) {
+                if (id - c * CW < CW - 4 && rank < room) {
                     wpos[c * PC + first + rank] = ws[h][k];
                     opos[c * PC + first + rank] = off;
+                    ++rank;
                 } else {
                     if (fits) {
                         ov[2 * e] = __float_as_uint(ws[h][k]);
@@ -484,7 +859,6 @@ __global__ __launch_bounds__(ROW_NT) void k_rowc_build(const int32_t* idx, const
                     }
                     ++e;
                 }
-                ++rank;
             }
         }
     for (int r = 0; r < 64; ++r) im[(size_t)r * ROW_NT] = __float_as_uint(wpos[r]);

@@ -4,7 +4,7 @@ layer's rows produced by workgroups on other XCDs (the barrier's release / acqui
 is what makes them visible).  Every layer of the chain is checked element by element
 against the oracle through the chain's own activations, and the persistent launch
 is bitwise equal to the explicit graph (layer by layer, and in its row profile),
-for the three resident-weight kernel families."""
+for the resident-weight kernel families."""
 import numpy as np
 import pytest
 import torch
@@ -65,3 +65,10 @@ def test_long_chain_chunked(P):
     # the chunked one-row-tile kernel (variant 6, two chunks) over 32 layers
     cfg = gen.CONFIGS["S3"].with_(n_neurons=18432, n_layers=32, rows=160, seed=79)
     _chain_vs_graph(P, cfg, 6)
+
+
+def test_long_chain_two_part(P):
+    # the uniform-weight two-part chunked kernel (variant 7, two chunks, 12 parts of
+    # 2048 in 6 workgroup parts) over 32 layers
+    cfg = gen.CONFIGS["S3"].with_(n_neurons=24576, n_layers=32, rows=160, seed=83)
+    _chain_vs_graph(P, cfg, 7)

@@ -1,10 +1,13 @@
 """Chunked one-row-tile kernel (16384 < N <= 65536, N a multiple of 2048; plan
 variant 6, rows staged in 2 or 4 chunks, paired neurons, a create-time bank order
-per chunk): every layer of its chain checked element by element against the oracle
-through the chain's own activations, with several rows per row stream, and the
-same for the wide-layer kernel on the same net; the engines bitwise equal to each
-other; a clamp the sums reach, a positive bias (no compaction), empty and one-row
-calls; the autotuner leaving every output unchanged."""
+per chunk) and its uniform-weight two-part form (variant 7: two parts per
+workgroup, the default where every layer has one weight value and N % 4096 == 0):
+every layer of their chains checked element by element against the oracle through
+the chain's own activations, with several rows per row stream, and the same for the
+wide-layer kernel on the same net; the engines bitwise equal to each other and
+variant 7 equal to variant 6 output for output; a clamp the sums reach, a positive
+bias (no compaction), empty and one-row calls; the autotuner leaving every output
+unchanged."""
 import numpy as np
 import pytest
 import torch
@@ -15,6 +18,10 @@ from tests.sdnn_gpu import DEV, check_chain, check_layer_sync, forward_layers, h
 pytestmark = pytest.mark.gpu
 
 WIDE = (32, 1024, 3)
+
+
+def default_variant(N, uniform=True):
+    return 7 if uniform and (N // 2048) % 2 == 0 else 6
 
 
 @pytest.fixture(scope="module")
@@ -39,21 +46,26 @@ def test_rowc_chain_layer_sync(P, N, layers, rows, cfgname):
     y0 = torch.from_numpy(y0h).to(DEV)
     net = P.Net(idx, w, b, max_rows=rows, ckpt_every=1)
     chunks = 2 if N <= 32768 else 4
-    assert net.plan["variant"] == 6 and net.plan["rows_per_tile"] == chunks, net.plan   # the default
+    v0 = default_variant(N)
+    assert net.plan["variant"] == v0 and net.plan["rows_per_tile"] == chunks, net.plan   # the default
     off = [0, rows // 5, rows // 5, rows // 5 + 1, rows]
     base = None
-    for m in ("persistent", "graph", "graph_merged", "eager"):
-        o, nz, ys = forward_layers(net, y0, batch_off=off, mode=m)
-        if base is None:
-            prof = o["layer_rows"].cpu().numpy()
-            print(f"N={N} rows={rows} profile {prof.tolist()}", flush=True)
-            check_chain(lay, cfg.clamp, ys, prof, nz, y0h)
-            dead = np.setdiff1d(np.arange(rows), nz)
-            assert (o["y"].cpu().numpy()[dead] == 0).all(), "dead rows must be exactly zero"
-            base = (o["y"].clone(), ys)
-        else:
-            assert torch.equal(o["y"], base[0]), m
-            assert all(np.array_equal(a, c) for a, c in zip(ys, base[1])), m
+    for v in sorted({v0, 6}, reverse=True):
+        net.set_plan(chunks, 1024, v)
+        for m in ("persistent", "graph", "graph_merged", "eager"):
+            o, nz, ys = forward_layers(net, y0, batch_off=off, mode=m)
+            if base is None:
+                prof = o["layer_rows"].cpu().numpy()
+                print(f"N={N} rows={rows} variant {v} profile {prof.tolist()}", flush=True)
+                check_chain(lay, cfg.clamp, ys, prof, nz, y0h)
+                dead = np.setdiff1d(np.arange(rows), nz)
+                assert (o["y"].cpu().numpy()[dead] == 0).all(), "dead rows must be exactly zero"
+                base = (o["y"].clone(), ys)
+            else:
+                # the other engines, and variant 6 against 7: the same slots in the same
+                # order with the same weight (padding adds w * 0 in 7 and 0 * y in 6)
+                assert torch.equal(o["y"], base[0]), (v, m)
+                assert all(np.array_equal(a, c) for a, c in zip(ys, base[1])), (v, m)
     # the wide-layer kernel on the same net (ascending order): also within the bounds
     net.set_plan(*WIDE)
     o, nz, ys = forward_layers(net, y0, batch_off=off, mode="persistent")
@@ -61,17 +73,23 @@ def test_rowc_chain_layer_sync(P, N, layers, rows, cfgname):
     net.close()
 
 
-def test_rowc_layer_sync_clamp_positive_bias_and_no_compaction(P):
+@pytest.mark.parametrize("weight", ["he", "const"])
+def test_rowc_layer_sync_clamp_positive_bias_and_no_compaction(P, weight):
     """Layer by layer with a clamp the sums reach and a positive bias (compaction off:
-    every row in every layer, the alive flags with no work list), on both chunk counts."""
+    every row in every layer, the alive flags with no work list), on both chunk counts;
+    He weights take variant 6 (the two-part form is refused), one weight value takes
+    variant 7."""
     for N in (20480, 40960):
         layers, rows, clamp = 3, 200, 1.5
-        cfg = gen.tiny_config(N, layers, rows, seed=N + 19, weight="he", bias=0.05, clamp=clamp, row_density=True)
+        cfg = gen.tiny_config(N, layers, rows, seed=N + 19, weight=weight, bias=0.05, clamp=clamp, row_density=True)
         idx, w, b = upload(cfg)
         lay = host_layers(idx, w, b)
         y0h = gen.make_inputs(cfg)
         net = P.Net(idx, w, b, max_rows=rows, clamp=clamp)
-        assert net.plan["variant"] == 6, net.plan
+        assert net.plan["variant"] == default_variant(N, weight == "const"), net.plan
+        if weight == "he":
+            with pytest.raises(Exception):
+                net.set_plan(2 if N <= 32768 else 4, 1024, 7)
         y = torch.from_numpy(y0h).to(DEV) * 1.5
         for l in range(layers):
             yn = net.layer(l, y)
@@ -93,21 +111,23 @@ def test_rowc_empty_and_single_row(P):
     lay = host_layers(idx, w, b)
     y0h = gen.make_inputs(cfg)
     net = P.Net(idx, w, b, max_rows=5, ckpt_every=1)
-    assert net.plan["variant"] == 6, net.plan
-    for rows in (1, 0, 5):
-        y0 = torch.from_numpy(y0h[:rows]).to(DEV)
-        for m in ("persistent", "graph"):
-            o, nz, ys = forward_layers(net, y0, mode=m)
-            if rows:
-                check_chain(lay, cfg.clamp, ys, o["layer_rows"].cpu().numpy(), nz, y0h[:rows])
-            else:
-                assert len(nz) == 0
+    assert net.plan["variant"] == 7, net.plan
+    for v in (7, 6):
+        net.set_plan(4, 1024, v)
+        for rows in (1, 0, 5):
+            y0 = torch.from_numpy(y0h[:rows]).to(DEV)
+            for m in ("persistent", "graph"):
+                o, nz, ys = forward_layers(net, y0, mode=m)
+                if rows:
+                    check_chain(lay, cfg.clamp, ys, o["layer_rows"].cpu().numpy(), nz, y0h[:rows])
+                else:
+                    assert len(nz) == 0
     net.close()
 
 
 def test_rowc_family_autotune_on_the_workload(P):
-    """At 65536 neurons the chunked kernel is alone in its family (its create-time
-    order): tuning on the workload's rows keeps it and leaves every output bitwise
+    """At 65536 neurons with one weight value the two-part kernel is alone in its
+    family: tuning on the workload's rows keeps it and leaves every output bitwise
     unchanged."""
     N, rows = 65536, 256
     cfg = gen.CONFIGS["S4"].with_(n_neurons=N, n_layers=2, rows=rows, seed=37)
@@ -118,7 +138,7 @@ def test_rowc_family_autotune_on_the_workload(P):
     torch.cuda.synchronize()
     plan = net.tune(rows, y_sample=y0)
     print("tuned plan", plan, flush=True)
-    assert plan["tuned_us"] > 0 and plan["variant"] == 6
+    assert plan["tuned_us"] > 0 and plan["variant"] == 7
     c = net.forward(y0, batch_off=[0, 100, rows])
     torch.cuda.synchronize()
     assert torch.equal(a["y"], c["y"])
