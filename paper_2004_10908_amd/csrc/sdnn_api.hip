@@ -932,6 +932,19 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
         }
     }
     if (lay.rowc) {
+        // the two-part kernel: whole pairs of parts and one weight value per layer (the
+        // per-layer flags go through the activation buffer)
+        bool uniform = false;
+        if ((N / ROW_PART) % 2 == 0 && (size_t)L <= (size_t)std::max<int64_t>(desc->max_rows, 1) * N) {
+            int32_t* flags = (int32_t*)n->act;
+            hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(L)), dim3(256), 0, s, flags, (int64_t)L, 0);
+            hipLaunchKernelGGL(k_weights_uniform, dim3(blocks_for(nnz)), dim3(256), 0, s, w, (int64_t)N * K, nnz, flags);
+            HIPCHK(hipGetLastError());
+            std::vector<int32_t> hf((size_t)L);
+            HIPCHK(hipMemcpyAsync(hf.data(), flags, (size_t)L * 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            uniform = std::all_of(hf.begin(), hf.end(), [](int32_t f) { return f == 0; });
+        }
         // neuron pairs of the chunked one-row-tile kernel, paired on the host from
         // per-neuron slot counts per chunk (computed on the device, max_rows layers at
         // a time through the activation buffer)
@@ -957,8 +970,8 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
             const int G = N / ROW_PART;
             const int64_t per2 = std::max<int64_t>(1, std::min<int64_t>({(int64_t)L, 2 * std::max<int64_t>(desc->max_rows, 1),
                                                                        (int64_t)65535}));
-            int32_t* status = n->flag + 3;                 // set by the builder if a list overflowed
-            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, status, (int64_t)1, 0);
+            int32_t* status = n->flag + 3;                 // [0] a list overflowed, [1] longest list
+            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, status, (int64_t)2, 0);
             for (int64_t l0 = 0; l0 < L; l0 += per2) {
                 const int64_t nl = std::min<int64_t>(per2, L - l0);
                 HIPCHK(hipMemcpyAsync(n->act, pairs.data() + (size_t)l0 * N / 2, (size_t)nl * N / 2 * 4,
@@ -966,6 +979,7 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
                 const size_t lp = (size_t)l0 * G;
                 hipLaunchKernelGGL(k_rowc_build, dim3(G, (unsigned)nl), dim3(ROW_NT), 0, s, idx + (size_t)l0 * N * K,
                                    w + (size_t)l0 * N * K, (const uint32_t*)n->act, (int32_t)N, (int32_t)C,
+                                   (int32_t)(uniform ? RU_ZERO : 0),
                                    n->rowc_img + lp * ROWC_IMG * ROW_NT, n->rowc_meta + lp * ROW_NT * 4,
                                    n->rowc_ovf + lp * ROWC_OVF_CAP * 2, status);
                 HIPCHK(hipGetLastError());
@@ -976,27 +990,16 @@ sdnn_status sdnn_create(const sdnn_desc* desc, const int32_t* idx, const float* 
             hipLaunchKernelGGL(k_rowc_sched, dim3((unsigned)std::min<int64_t>(4096, (tasks + 63) / 64)), dim3(64), 0, s,
                                n->rowc_img, n->rowc_meta, tasks, (int32_t)C);
             HIPCHK(hipGetLastError());
-            int32_t over = 0;
-            HIPCHK(hipMemcpyAsync(&over, status, 4, hipMemcpyDeviceToHost, s));
+            int32_t st[2] = {0, 0};
+            HIPCHK(hipMemcpyAsync(st, status, 8, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            n->rowc = over == 0;
+            n->rowc = st[0] == 0;
             n->rowc_chunks = C;
-        }
-        // the two-part kernel: whole pairs of parts and one weight value per layer (the
-        // per-layer flags go through the activation buffer)
-        if (n->rowc && (N / ROW_PART) % 2 == 0 && (size_t)L <= (size_t)std::max<int64_t>(desc->max_rows, 1) * N) {
-            int32_t* flags = (int32_t*)n->act;
-            hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(L)), dim3(256), 0, s, flags, (int64_t)L, 0);
-            hipLaunchKernelGGL(k_weights_uniform, dim3(blocks_for(nnz)), dim3(256), 0, s, w, (int64_t)N * K, nnz, flags);
-            HIPCHK(hipGetLastError());
-            std::vector<int32_t> hf((size_t)L);
-            HIPCHK(hipMemcpyAsync(hf.data(), flags, (size_t)L * 4, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            if (std::all_of(hf.begin(), hf.end(), [](int32_t f) { return f == 0; })) {
-                // padding reads the chunk buffer's last word, which that kernel keeps zero
-                const int64_t lanes = (int64_t)L * (N / ROW_PART) * ROW_NT;
+            if (n->rowc && uniform && st[1] <= RU_OVF_CAP) {
+                // padding reads the zero words at the end of the two-part kernel's buffers
+                const int64_t lanes = (int64_t)L * G * ROW_NT;
                 hipLaunchKernelGGL(k_rowu_pads, dim3(blocks_for(lanes)), dim3(256), 0, s, n->rowc_img, lanes,
-                                   (uint32_t)(4 * (N / C - 1)));
+                                   (uint32_t)(4 * (N / C - RU_ZERO)));
                 HIPCHK(hipGetLastError());
                 HIPCHK(hipStreamSynchronize(s));
                 n->rowu = true;

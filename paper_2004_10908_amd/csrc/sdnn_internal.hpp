@@ -205,10 +205,15 @@ template <int C>
 __global__ void k_chain_rowc(ChainArgs c);
 __global__ void k_rowc_counts(const int32_t* idx, int64_t neurons, int32_t N, int32_t C, uint32_t* counts);
 __global__ void k_rowc_build(const int32_t* idx, const float* w, const uint32_t* pairs, int32_t N, int32_t C,
-                             uint32_t* img, uint32_t* meta, uint32_t* ovf, int32_t* status);
+                             int32_t disp, uint32_t* img, uint32_t* meta, uint32_t* ovf, int32_t* status);
 // The uniform-weight two-part kernel (sdnn_rowc.hip): the chunked kernel's lane
 // images, two parts per workgroup (4096 neurons), for nets whose layers each have a
 // single weight value; N % 4096 == 0.
+// The last RU_ZERO ids of every chunk are staged outside the buffer (zero words in
+// their place, one per LDS bank); a workgroup's two overflow lists take at most
+// RU_OVF_CAP 4-byte entries each, beside the side slots at the end of LDS.
+constexpr int RU_ZERO = 32;
+constexpr int RU_OVF_CAP = (int)((LDS_BYTES - 2 * 4 * RU_ZERO - ROWC_OVF) / 8);
 template <int C>
 __global__ void k_layer_rowu(LayerArgs a);
 template <int C>

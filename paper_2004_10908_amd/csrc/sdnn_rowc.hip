@@ -400,12 +400,15 @@ template __global__ void k_chain_rowc<4>(ChainArgs);
 // of the chunked kernel's lane images, so a workgroup computes 4096 neurons and each
 // row is staged from L2 once per 4096 neurons instead of once per 2048 (the staging
 // is what bounds the chunked kernel at 65536 neurons).  What differs from it:
-//  * padding positions read a zero word: the last 16 bytes of every staged chunk go
-//    to a side slot instead of the buffer, so the buffer's last word stays zero; the
-//    builder makes every slot on those 4 ids an overflow entry, and k_rowu_pads
-//    points the padding offsets at that word once per net;
+//  * padding positions read zero words: the last RU_ZERO ids (128 bytes) of every
+//    staged chunk go to a side slot instead of the buffer, so the buffer ends in 32
+//    zero words, one in each LDS bank; the builder makes every slot on those ids an
+//    overflow entry, and k_rowu_pads points each padding offset at the zero word of
+//    the bank the create-time order gave it (one shared word would add a second
+//    pass to a third of the reads: C4 layer 8.4 ms);
 //  * overflow entries are 4 bytes (offset | owner << 16 | side << 17), the lists of
-//    both sub-parts in the LDS one part's 8-byte list takes;
+//    both sub-parts (at most RU_OVF_CAP entries each) in the LDS one part's 8-byte
+//    list takes;
 //  * one output stage of 4096 floats: it is written after the last chunk step of a
 //    row and read after the first barrier of the next one, C - 1 >= 1 barriers later.
 // Every neuron sums its slots in the images' order with fused multiply-adds by w, as
@@ -413,8 +416,8 @@ template __global__ void k_chain_rowc<4>(ChainArgs);
 // there), so the two give equal outputs.
 namespace {
 
-constexpr uint32_t RU_SIDE = ROW_SCAL + 128;                     // [2][16 bytes], one per buffer
-constexpr uint32_t RU_OVF_HALF = (uint32_t)ROWC_OVF_CAP * 4u;    // one sub-part's 4-byte entries
+constexpr uint32_t RU_SIDE = (uint32_t)LDS_BYTES - 2u * 4u * RU_ZERO;   // [2][RU_ZERO floats], one per buffer
+constexpr uint32_t RU_OVF_HALF = (uint32_t)RU_OVF_CAP * 4u;              // one sub-part's 4-byte entries
 
 struct RowuPair {
     uint32_t o[32];    // 64 positions: 16-bit LDS byte offsets within the chunk buffer
@@ -427,7 +430,7 @@ struct RowuPair {
 
 // Pair `tid` of sub-part sp (0 or 1) of the workgroup, image part `ip`; the
 // sub-part's overflow list goes to LDS with the side bit set on entries of a chunk's
-// last 4 ids.
+// last RU_ZERO ids.
 __device__ __forceinline__ void rowu_load(const LayerArgs& a, int ip, int sp, int tid, int CW, RowuPair& n) {
     const uint32_t* img = a.rowc_img + (size_t)ip * ROWC_IMG * ROW_NT + tid;
 #pragma unroll
@@ -440,8 +443,8 @@ __device__ __forceinline__ void rowu_load(const LayerArgs& a, int ip, int sp, in
     n.ba = a.b[ip * ROW_PART + (int)(m.x & 0xffffu)];
     n.bb = a.b[ip * ROW_PART + (int)(m.x >> 16)];
     const uint2* src = reinterpret_cast<const uint2*>(a.rowc_ovf + (size_t)ip * ROWC_OVF_CAP * 2);
-    const uint32_t last = 4u * (uint32_t)(CW - 4);
-    for (int e = tid; e < ROWC_OVF_CAP; e += ROW_NT) {
+    const uint32_t last = 4u * (uint32_t)(CW - RU_ZERO);
+    for (int e = tid; e < RU_OVF_CAP; e += ROW_NT) {
         const uint32_t y = src[e].y;
         *lds_at<uint32_t>(ROWC_OVF + (uint32_t)sp * RU_OVF_HALF + 4u * (uint32_t)e) =
             y | ((y & 0xffffu) >= last ? (1u << 17) : 0u);
@@ -483,11 +486,10 @@ __device__ __forceinline__ void rowu_group(const RowuPair& n, float wu, uint32_t
     if constexpr (G + 1 < PC / RS) rowu_group<C, CH, RS, G + 1>(n, wu, buf, splitc, cur, acca, accb, v, hook);
 }
 
-// Chunk CH of the row (buffer at `buf`, its last 16 bytes at `side`) for one pair:
-// its positions, then its overflow entries.
+// Chunk CH of the row (buffer at `buf`) for one pair: its positions.
 template <int C, int CH, int RS, typename Hook>
-__device__ __forceinline__ void rowu_chunk(const RowuPair& n, float wu, uint32_t buf, uint32_t side, float& acca,
-                                           float& accb, Hook&& hook) {
+__device__ __forceinline__ void rowu_positions(const RowuPair& n, float wu, uint32_t buf, float& acca, float& accb,
+                                               Hook&& hook) {
     constexpr int PC = 64 / C;
     uint32_t splitc = byte_of(n.split, CH);
     __asm__ volatile("" : "+v"(splitc));
@@ -498,18 +500,49 @@ __device__ __forceinline__ void rowu_chunk(const RowuPair& n, float wu, uint32_t
     const bool none = splitc == (uint32_t)PC;
     acca = none ? cur : acca;
     accb = none ? accb : cur;
-    const int cnt = (int)byte_of(n.ocnt, CH);
+}
+
+// LDS byte address of the pair's first overflow entry of chunk CH.
+template <int CH>
+__device__ __forceinline__ uint32_t rowu_first_entry(const RowuPair& n) {
     uint32_t ea = n.obase;
 #pragma unroll
     for (int c = 0; c < CH; ++c) ea += 4u * byte_of(n.ocnt, c);
-    for (int e = 0; e < cnt; ++e) {
-        const uint32_t en = *lds_at<uint32_t>(ea + 4u * (uint32_t)e);
+    return ea;
+}
+
+// The overflow entries of chunk CH of both pairs, one entry of each per pass (two
+// independent chains of dependent LDS reads instead of one after the other; each
+// pair's entries still in their order).  en0 / en1: the first entries, read by the
+// caller ahead (a lane without one read a word it does not use).
+template <int CH>
+__device__ __forceinline__ void rowu_overflow(const RowuPair& n0, const RowuPair& n1, float wu, uint32_t buf,
+                                              uint32_t side, uint32_t ea0, uint32_t ea1, uint32_t en0, uint32_t en1,
+                                              float& acca0, float& accb0, float& acca1, float& accb1) {
+    const int cnt0 = (int)byte_of(n0.ocnt, CH), cnt1 = (int)byte_of(n1.ocnt, CH);
+    const int cmax = max(cnt0, cnt1);
+    auto addr = [&](uint32_t en) {
         const uint32_t off = en & 0xffffu;
-        const float x = row_lds_read((en >> 17) ? side + (off & 15u) : (buf | off));
-        if ((en >> 16) & 1u)
-            accb = fmaf(wu, x, accb);
-        else
-            acca = fmaf(wu, x, acca);
+        return (en >> 17) ? side + (off & (4u * RU_ZERO - 1u)) : (buf | off);
+    };
+    for (int e = 0; e < cmax; ++e) {
+        const float x0 = row_lds_read(addr(en0));
+        const float x1 = row_lds_read(addr(en1));
+        if (e < cnt0) {
+            if ((en0 >> 16) & 1u)
+                accb0 = fmaf(wu, x0, accb0);
+            else
+                acca0 = fmaf(wu, x0, acca0);
+        }
+        if (e < cnt1) {
+            if ((en1 >> 16) & 1u)
+                accb1 = fmaf(wu, x1, accb1);
+            else
+                acca1 = fmaf(wu, x1, acca1);
+        }
+        // the next entries (a lane past its count reads its last one again)
+        en0 = *lds_at<uint32_t>(ea0 + 4u * (uint32_t)min(e + 1, max(cnt0 - 1, 0)));
+        en1 = *lds_at<uint32_t>(ea1 + 4u * (uint32_t)min(e + 1, max(cnt1 - 1, 0)));
     }
 }
 
@@ -544,11 +577,18 @@ __device__ __forceinline__ void run_layer_rowu(const LayerArgs& a, int R) {
     rowu_load(a, 2 * p + 1, 1, tid, CW, n1);
 #pragma unroll
     for (int s = 0; s < 32; ++s) __asm__ volatile("" : "+v"(n0.o[s]), "+v"(n1.o[s]));   // keep resident
-    // the zero words: the last 16 bytes of both buffers, which no copy writes
-    if (tid < 8) *lds_at<float>((uint32_t)(tid >> 2) * ROW_BUF_BYTES + 4u * (uint32_t)(CW - 4 + (tid & 3))) = 0.f;
+    // the zero words: the last RU_ZERO words of both buffers, which no copy writes
+    if (tid < 2 * RU_ZERO)
+        *lds_at<float>((uint32_t)(tid / RU_ZERO) * ROW_BUF_BYTES + 4u * (uint32_t)(CW - RU_ZERO + tid % RU_ZERO)) = 0.f;
 
-    const int ncopy = CW / 256;                        // 1 KB copies per chunk
-    const int mycopies = wave < ncopy ? (ncopy - wave + RC_WAVES - 1) / RC_WAVES : 0;
+    // a chunk's 1 KB pieces: all but the last as plain copies spread over the waves,
+    // the last one (its last 128 bytes, lanes 56..63, to the buffer's side slot) by
+    // the wave left with one copy fewer, before its compute (control flow among the
+    // plain copies, which run between the compute groups, cost 0.7 ms per C4 layer)
+    const int ncopy = CW / 256;
+    const int nplain = ncopy - 1;
+    const int mycopies = wave < nplain ? (nplain - wave + RC_WAVES - 1) / RC_WAVES : 0;
+    const int lastw = nplain % RC_WAVES;
     auto pos_row = [&](int i) -> int { return a.row_base + q + i * S; };   // identity work list
     auto prefetch = [&](int i) {
         if (a.list_in && wave == 0 && lane == 0) row_copy4(a.list_in + q + i * S, RC_S_RING + 4u * (uint32_t)(i % 3));
@@ -557,20 +597,22 @@ __device__ __forceinline__ void run_layer_rowu(const LayerArgs& a, int R) {
         return a.list_in ? __builtin_amdgcn_readfirstlane(s_ring[i % 3]) : pos_row(i);
     };
     const uint64_t ybase = uniform_ptr(a.yin);
-    const int rot = (int)(((int64_t)p * ncopy) / G);
-    // this wave's k-th copy of a chunk into the buffer at byte `buf`; the chunk's last
-    // piece leaves its last 16 bytes (lane 63's) to the buffer's side slot
-    auto copy = [&](uint64_t chunk_src, uint32_t buf, uint32_t side, int k) {
+    const int rot = (int)(((int64_t)p * nplain) / G);
+    // this wave's k-th plain copy of a chunk into the buffer at byte `buf`
+    auto copy = [&](uint64_t chunk_src, uint32_t buf, int k) {
         int cc = wave + k * RC_WAVES;
-        if (cc >= ncopy) return;
+        if (cc >= nplain) return;
         cc += rot;
-        if (cc >= ncopy) cc -= ncopy;
-        const uint64_t src = chunk_src + 1024ull * (uint32_t)cc;
-        const uint32_t dst = buf + 1024u * (uint32_t)cc;
-        if (cc != ncopy - 1 || lane < 63)
-            row_copy16(src, 16u * (uint32_t)lane, dst);
+        if (cc >= nplain) cc -= nplain;
+        row_copy16(chunk_src + 1024ull * (uint32_t)cc, 16u * (uint32_t)lane, buf + 1024u * (uint32_t)cc);
+    };
+    auto copy_last = [&](uint64_t chunk_src, uint32_t buf, uint32_t side) {
+        constexpr int L0 = 64 - RU_ZERO / 4;               // first lane of the displaced bytes
+        const uint64_t src = chunk_src + 1024ull * (uint32_t)nplain;
+        if (lane < L0)
+            row_copy16(src, 16u * (uint32_t)lane, buf + 1024u * (uint32_t)nplain);
         else
-            row_copy16(src, 16u * (uint32_t)lane, side - 16u * 63u);   // lands at `side`
+            row_copy16(src, 16u * (uint32_t)lane, side - 16u * (uint32_t)L0);   // lands at `side`
     };
     auto chunk_src = [&](int row, int c) -> uint64_t {
         uint64_t s = ybase + 4ull * ((uint64_t)(uint32_t)row * (uint64_t)N + (uint64_t)(c * CW));
@@ -630,7 +672,8 @@ __device__ __forceinline__ void run_layer_rowu(const LayerArgs& a, int R) {
     int row_c = ring_row(0);
     {
         const uint64_t cs = chunk_src(row_c, 0);
-        for (int k = 0; k < mycopies; ++k) copy(cs, 0u, RU_SIDE, k);
+        for (int k = 0; k < mycopies; ++k) copy(cs, 0u, k);
+        if (wave == lastw) copy_last(cs, 0u, RU_SIDE);
     }
     int row_p = 0;
     for (int i = 0; i < ntile; ++i) {
@@ -641,7 +684,7 @@ __device__ __forceinline__ void run_layer_rowu(const LayerArgs& a, int R) {
             constexpr int CH = decltype(cc)::value;
             uint32_t buf = (uint32_t)(CH & 1) * ROW_BUF_BYTES;
             __asm__ volatile("" : "+s"(buf));
-            const uint32_t side = RU_SIDE + 16u * (uint32_t)(CH & 1);
+            const uint32_t side = RU_SIDE + 4u * RU_ZERO * (uint32_t)(CH & 1);
             __asm__ volatile("s_waitcnt vmcnt(0)" : : : "memory");   // this wave's copies of the chunk have landed
             __syncthreads();                                        // everyone's have; the other buffer is free
             if constexpr (CH == 0) {
@@ -660,16 +703,21 @@ __device__ __forceinline__ void run_layer_rowu(const LayerArgs& a, int R) {
             const bool next = CH + 1 < C || more;
             const uint64_t nsrc = chunk_src(CH + 1 < C ? row_c : row_n, CH + 1 < C ? CH + 1 : 0);
             const uint32_t nbuf = (uint32_t)((CH + 1) & 1) * ROW_BUF_BYTES;
-            const uint32_t nside = RU_SIDE + 16u * (uint32_t)((CH + 1) & 1);
+            const uint32_t nside = RU_SIDE + 4u * RU_ZERO * (uint32_t)((CH + 1) & 1);
             int myc = next ? mycopies : 0;
             __asm__ volatile("" : "+s"(myc));
+            if (next && wave == lastw) copy_last(nsrc, nbuf, nside);
             auto hook = [&](int g) {
                 if (g == 0)
-                    for (int k = 0; k < myc; ++k) copy(nsrc, nbuf, nside, k);
+                    for (int k = 0; k < myc; ++k) copy(nsrc, nbuf, k);
             };
             auto nohook = [](int) {};
-            rowu_chunk<C, CH, RS>(n0, wu, buf, side, acca0, accb0, hook);
-            rowu_chunk<C, CH, RS>(n1, wu, buf, side, acca1, accb1, nohook);
+            const uint32_t ea0 = rowu_first_entry<CH>(n0), ea1 = rowu_first_entry<CH>(n1);
+            rowu_positions<C, CH, RS>(n0, wu, buf, acca0, accb0, hook);
+            // the first overflow entries, read while the second pair's positions run
+            const uint32_t en0 = *lds_at<uint32_t>(ea0), en1 = *lds_at<uint32_t>(ea1);
+            rowu_positions<C, CH, RS>(n1, wu, buf, acca1, accb1, nohook);
+            rowu_overflow<CH>(n0, n1, wu, buf, side, ea0, ea1, en0, en1, acca0, accb0, acca1, accb1);
         };
         step(std::integral_constant<int, 0>{});
         step(std::integral_constant<int, 1>{});
@@ -737,16 +785,18 @@ template __global__ void k_layer_rowu<4>(LayerArgs);
 template __global__ void k_chain_rowu<2>(ChainArgs);
 template __global__ void k_chain_rowu<4>(ChainArgs);
 
-// Points every padding position (weight 0) of the lane images at byte offset `zoff`
-// of the chunk buffer, the zero word of the uniform-weight kernel (the chunked
-// kernel multiplies padding by 0 wherever it points).  One thread per lane image.
-__global__ void k_rowu_pads(uint32_t* img, int64_t lanes, uint32_t zoff) {
+// Points every padding position (weight 0) of the lane images at the zero word of
+// its LDS bank among the uniform-weight kernel's RU_ZERO zero words, which start at
+// byte `zbase` of the chunk buffer (the chunked kernel multiplies padding by 0
+// wherever it points).  One thread per lane image.
+__global__ void k_rowu_pads(uint32_t* img, int64_t lanes, uint32_t zbase) {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < lanes; t += (int64_t)gridDim.x * blockDim.x) {
         uint32_t* im = img + (t / ROW_NT) * (int64_t)ROWC_IMG * ROW_NT + t % ROW_NT;
+        auto zero_word = [&](uint32_t off) { return zbase + 4u * ((off >> 2) & (RU_ZERO - 1u)); };
         for (int r = 0; r < 32; ++r) {
             uint32_t o = im[(size_t)(64 + r) * ROW_NT];
-            if ((im[(size_t)(2 * r) * ROW_NT] & 0x7fffffffu) == 0u) o = (o & 0xffff0000u) | zoff;
-            if ((im[(size_t)(2 * r + 1) * ROW_NT] & 0x7fffffffu) == 0u) o = (o & 0xffffu) | (zoff << 16);
+            if ((im[(size_t)(2 * r) * ROW_NT] & 0x7fffffffu) == 0u) o = (o & 0xffff0000u) | zero_word(o & 0xffffu);
+            if ((im[(size_t)(2 * r + 1) * ROW_NT] & 0x7fffffffu) == 0u) o = (o & 0xffffu) | (zero_word(o >> 16) << 16);
             im[(size_t)(64 + r) * ROW_NT] = o;
         }
     }
@@ -779,14 +829,15 @@ __global__ void k_rowc_counts(const int32_t* idx, int64_t neurons, int32_t N, in
 // The lane images of one (part, layer) = (blockIdx.x, blockIdx.y), one thread per
 // pair (lane): positions per chunk (A's slots, then B's, then weight-0 padding),
 // the pair words and the part's overflow list, entries of a lane in chunk order
-// (A's excess, then B's) and lanes in order.  Slots on a chunk's last 4 ids are
-// always overflow entries (the uniform-weight kernel keeps those 16 bytes of a
-// staged chunk outside the buffer and a zero word in their place).  A list longer
-// than ROWC_OVF_CAP keeps only what fits, a lane whose entries do not all fit keeps
-// none, and `status` is set to 1 (the host then does not use the images).
+// (A's excess, then B's) and lanes in order.  Slots on a chunk's last `disp` ids
+// (0, or RU_ZERO for the uniform-weight kernel, which keeps those bytes of a staged
+// chunk outside the buffer and zero words in their place) are always overflow
+// entries.  A list longer than ROWC_OVF_CAP keeps only what fits, a lane whose
+// entries do not all fit keeps none, and status[0] is set to 1 (the host then does
+// not use the images); status[1] becomes the longest list's length.
 __global__ __launch_bounds__(ROW_NT) void k_rowc_build(const int32_t* idx, const float* w, const uint32_t* pairs,
-                                                       int32_t N, int32_t C, uint32_t* img, uint32_t* meta,
-                                                       uint32_t* ovf, int32_t* status) {
+                                                       int32_t N, int32_t C, int32_t disp, uint32_t* img,
+                                                       uint32_t* meta, uint32_t* ovf, int32_t* status) {
     __shared__ int s_tot[RC_WAVES];
     const int p = blockIdx.x, l = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int parts = gridDim.x;
@@ -802,7 +853,7 @@ __global__ __launch_bounds__(ROW_NT) void k_rowc_build(const int32_t* idx, const
             const int id = max(ids[h][k], 0);
             const int c = min(id / CW, C - 1);
             cnt[h][c] += 1;
-            cntp[h][c] += (id - c * CW < CW - 4) ? 1 : 0;
+            cntp[h][c] += (id - c * CW < CW - disp) ? 1 : 0;
         }
     uint32_t split = 0u, ocnt = 0u;
     int tot = 0;
@@ -827,6 +878,7 @@ __global__ __launch_bounds__(ROW_NT) void k_rowc_build(const int32_t* idx, const
     for (int x = 0; x < wave; ++x) base += s_tot[x];
     const bool fits = base + tot <= ROWC_OVF_CAP;
     if (!fits) atomicOr(status, 1);
+    atomicMax(status + 1, base + tot);
     const size_t pl = (size_t)l * parts + p;
     uint32_t* im = img + pl * ROWC_IMG * ROW_NT + tid;
     uint32_t* ov = ovf + pl * ROWC_OVF_CAP * 2;
@@ -848,7 +900,7 @@ __global__ __launch_bounds__(ROW_NT) void k_rowc_build(const int32_t* idx, const
                 const int id = ids[h][k];
                 if (min(max(id, 0) / CW, C - 1) != c) continue;
                 const uint32_t off = (4u * (uint32_t)(id - c * CW)) & 0xffffu;
-                if (id - c * CW < CW - 4 && rank < room) {
+                if (id - c * CW < CW - disp && rank < room) {
                     wpos[c * PC + first + rank] = ws[h][k];
                     opos[c * PC + first + rank] = off;
                     ++rank;
