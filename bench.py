@@ -100,7 +100,7 @@ def forward_bytes(prof, N, L):
 
 # committed rocprofv3 counter summaries of the persistent chain kernels, per
 # headline workload: (summary, kernel source it was taken with)
-PROFILES = {"C4": "k_chain_rowc_C4_forward.md", "C2": "k_chain_sched_C2_forward.md"}
+PROFILES = {"C4": "k_chain_rowu_C4_forward.md", "C2": "k_chain_sched_C2_forward.md"}
 # the sources the forward kernels are built from (hashed together)
 KERNEL_SOURCES = ("sdnn_fwd.hip", "sdnn_rowc.hip", "sdnn_device.hpp", "sdnn_internal.hpp")
 

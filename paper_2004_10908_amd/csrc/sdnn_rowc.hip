@@ -878,7 +878,7 @@ __global__ __launch_bounds__(ROW_NT) void k_rowc_build(const int32_t* idx, const
     for (int x = 0; x < wave; ++x) base += s_tot[x];
     const bool fits = base + tot <= ROWC_OVF_CAP;
     if (!fits) atomicOr(status, 1);
-    atomicMax(status + 1, base + tot);
+    if (tid == ROW_NT - 1) atomicMax(status + 1, base + tot);   // the last lane's end: the list's length
     const size_t pl = (size_t)l * parts + p;
     uint32_t* im = img + pl * ROWC_IMG * ROW_NT + tid;
     uint32_t* ov = ovf + pl * ROWC_OVF_CAP * 2;
