@@ -143,3 +143,32 @@ def test_rowc_family_autotune_on_the_workload(P):
     torch.cuda.synchronize()
     assert torch.equal(a["y"], c["y"])
     net.close()
+
+
+def test_two_part_needs_one_weight_in_every_layer(P):
+    """One weight value in every layer but one (a single weight of the last layer
+    changed): the two-part form is refused, variant 6 serves the net, and its chain
+    still matches the oracle; with the weight restored the two-part form is the
+    default again and gives the same outputs."""
+    N, layers, rows = 20480, 3, 120
+    cfg = gen.CONFIGS["S4"].with_(n_neurons=N, n_layers=layers, rows=rows, seed=97)
+    idx, w, b = upload(cfg)
+    y0h = gen.make_inputs(cfg)
+    y0 = torch.from_numpy(y0h).to(DEV)
+    w_odd = w.clone()
+    w_odd[layers - 1, 123, 7] *= 1.5
+    lay = host_layers(idx, w_odd, b)
+    net = P.Net(idx, w_odd, b, max_rows=rows, ckpt_every=1)
+    assert net.plan["variant"] == 6, net.plan
+    with pytest.raises(Exception):
+        net.set_plan(2, 1024, 7)
+    o, nz, ys = forward_layers(net, y0, mode="persistent")
+    check_chain(lay, cfg.clamp, ys, o["layer_rows"].cpu().numpy(), nz, y0h)
+    net.close()
+    net = P.Net(idx, w, b, max_rows=rows, ckpt_every=1)
+    assert net.plan["variant"] == 7, net.plan
+    a = forward_layers(net, y0, mode="persistent")[0]["y"].clone()
+    net.set_plan(2, 1024, 6)
+    c = forward_layers(net, y0, mode="persistent")[0]["y"]
+    assert torch.equal(a, c)
+    net.close()
