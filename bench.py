@@ -101,14 +101,15 @@ def forward_bytes(prof, N, L):
 # committed rocprofv3 counter summaries of the persistent chain kernels, per
 # headline workload: (summary, kernel source it was taken with)
 PROFILES = {"C4": "k_chain_rowu_C4_forward.md", "C2": "k_chain_sched_C2_forward.md"}
-# the sources the forward kernels are built from (hashed together)
-KERNEL_SOURCES = ("sdnn_fwd.hip", "sdnn_rowc.hip", "sdnn_device.hpp", "sdnn_internal.hpp")
+# the sources each profiled chain kernel is built from (hashed together)
+KERNEL_SOURCES = {"C4": ("sdnn_rowc.hip", "sdnn_device.hpp", "sdnn_internal.hpp"),
+                  "C2": ("sdnn_fwd.hip", "sdnn_device.hpp", "sdnn_internal.hpp")}
 
 
-def kernel_source_sha256():
+def kernel_source_sha256(workload):
     import hashlib
     h = hashlib.sha256()
-    for src in KERNEL_SOURCES:
+    for src in KERNEL_SOURCES[workload]:
         h.update(open(os.path.join(ROOT, "paper_2004_10908_amd", "csrc", src), "rb").read())
     return h.hexdigest()
 
@@ -128,7 +129,7 @@ def measured_traffic(workload, kernel):
         k, _, v = line.strip().partition(": ")
         if k in ("traffic_bytes_per_launch", "kernel_source_sha256", "kernel"):
             vals[k] = v.strip()
-    if len(vals) != 3 or vals["kernel"] != kernel or kernel_source_sha256() != vals["kernel_source_sha256"]:
+    if len(vals) != 3 or vals["kernel"] != kernel or kernel_source_sha256(workload) != vals["kernel_source_sha256"]:
         return None
     return int(vals["traffic_bytes_per_launch"])
 
