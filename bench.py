@@ -101,8 +101,10 @@ def forward_bytes(prof, N, L):
 # committed rocprofv3 counter summaries of the persistent chain kernels, per
 # headline workload: (summary, kernel source it was taken with)
 PROFILES = {"C4": "k_chain_rowu_C4_forward.md", "C2": "k_chain_sched_C2_forward.md"}
-# the sources each profiled chain kernel is built from (hashed together)
-KERNEL_SOURCES = {"C4": ("sdnn_rowc.hip", "sdnn_device.hpp", "sdnn_internal.hpp"),
+# the sources each profiled chain kernel is built from (hashed together); for the
+# chunked kernel also its create-time neuron pairing, whose order sets how the
+# parts of a row stream drift apart and so how often rows are fetched again
+KERNEL_SOURCES = {"C4": ("sdnn_rowc.hip", "sdnn_device.hpp", "sdnn_internal.hpp", "sdnn_rowsched.hip"),
                   "C2": ("sdnn_fwd.hip", "sdnn_device.hpp", "sdnn_internal.hpp")}
 
 

@@ -332,6 +332,10 @@ int64_t build_row_schedule(const int32_t* idx, int N, int L, uint8_t* perm) {
 //    the least squared deviation from 16 per chunk), searched among the count
 //    vectors within distance 2 (per chunk) of the ideal complement 16 - count,
 //    nearest first, or among all unpaired neurons when none is that close.
+// Then the part's pairs are put in order of decreasing overflow: a wave runs its
+// overflow loop as often as its busiest lane needs, so pairs with excess share
+// waves (for random C = 4 patterns three quarters of the loop trips of the
+// pairing's own order, which puts the most unbalanced neurons first).
 namespace {
 
 uint32_t cnt_of(uint32_t v, int c) { return (v >> (8 * c)) & 0xffu; }
@@ -455,6 +459,8 @@ int build_rowc_pairs(const uint32_t* counts, int N, int L, int C, uint32_t* pair
                 const uint32_t* cnt = counts + (size_t)l * N + (size_t)p * ROW_PART;
                 uint32_t* out = pairs + (size_t)l * (N / 2) + (size_t)p * (ROW_PART / 2);
                 worst[t] = std::max(worst[t], pair_part(cnt, ROW_PART, C, out, pb));
+                auto excess = [cnt, C](uint32_t pr) { return pair_cost(cnt[pr & 0xffffu], cnt[pr >> 16], C).first; };
+                std::stable_sort(out, out + ROW_PART / 2, [&](uint32_t x, uint32_t y) { return excess(x) > excess(y); });
             }
         });
     }

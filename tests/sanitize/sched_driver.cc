@@ -64,7 +64,8 @@ int main() {
         bad += worst < K || tworst < 1 || cost < (long long)L * ((N + 31) / 32) * K;
     }
     // neuron pairs of the chunked kernel: every neuron of a part in exactly one pair,
-    // the returned overflow is the largest part's, and it fits the LDS list
+    // pairs in order of non-increasing overflow, the returned overflow is the largest
+    // part's, and it fits the LDS list
     for (int N : {20480, 32768, 65536}) {
         const int L = 2, C = N <= 32768 ? 2 : 4, CW = N / C, PC = 64 / C, PART = 2048;
         std::vector<uint32_t> cnt((size_t)L * N);
@@ -82,7 +83,7 @@ int main() {
         for (int l = 0; l < L; ++l)
             for (int p = 0; p < N / PART; ++p) {
                 std::vector<int> seen(PART, 0);
-                int ov = 0;
+                int ov = 0, prev = 1 << 30;
                 for (int i = 0; i < PART / 2; ++i) {
                     const uint32_t pr = pairs[(size_t)l * N / 2 + (size_t)p * PART / 2 + i];
                     const int a = (int)(pr & 0xffffu), b = (int)(pr >> 16);
@@ -91,10 +92,14 @@ int main() {
                     ++seen[a];
                     ++seen[b];
                     const uint32_t ca = cnt[(size_t)l * N + p * PART + a], cb = cnt[(size_t)l * N + p * PART + b];
+                    int mine_ov = 0;
                     for (int c = 0; c < C; ++c) {
                         const int t = (int)((ca >> (8 * c)) & 255u) + (int)((cb >> (8 * c)) & 255u);
-                        ov += t > PC ? t - PC : 0;
+                        mine_ov += t > PC ? t - PC : 0;
                     }
+                    bad += mine_ov > prev;
+                    prev = mine_ov;
+                    ov += mine_ov;
                 }
                 for (int j = 0; j < PART; ++j) bad += seen[j] != 1;
                 mine = std::max(mine, ov);
